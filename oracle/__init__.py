@@ -1,0 +1,195 @@
+"""CPU oracle for the Swendsen-Wang sweep of the 2D q-state Potts model.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The library
+under ``paper_1208_2080_amd`` never touches it, and it shares no code with the
+HIP path.
+
+The arithmetic lives in ``sw_oracle.c`` (plain C, one thread); this module only
+compiles it with gcc and marshals arguments.  It follows the paper's three SW
+steps (Sec. 2): bond activation, Hoshen-Kopelman cluster labelling with the
+smallest label as the proper label, and a random new state per cluster, with
+the energy of Eq. (1) counted as the number of unsatisfied bonds.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "sw_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.or_philox.argtypes = [u32p, u32p, u32p]
+        L.or_philox.restype = None
+        L.or_threshold.argtypes = [ctypes.c_double]
+        L.or_threshold.restype = ctypes.c_uint64
+        L.or_state_of_draw.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+        L.or_state_of_draw.restype = ctypes.c_uint32
+        L.or_newspin.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32]
+        L.or_newspin.restype = ctypes.c_uint32
+        L.or_initspin.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]
+        L.or_initspin.restype = ctypes.c_uint32
+        L.or_bond_draws.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, u32p, u32p]
+        L.or_bond_draws.restype = None
+        L.or_init.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, u8p]
+        L.or_init.restype = ctypes.c_int
+        L.or_observe.argtypes = [ctypes.c_uint32, ctypes.c_uint32, u8p, i64p]
+        L.or_observe.restype = None
+        L.or_label.argtypes = [ctypes.c_uint32, u8p, u8p, u32p]
+        L.or_label.restype = None
+        L.or_sweep.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64,
+                               ctypes.c_uint32, u8p, u8p, u8p, u32p, i64p]
+        L.or_sweep.restype = ctypes.c_int
+        L.or_run.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64,
+                             ctypes.c_uint32, ctypes.c_uint32, u8p, i64p]
+        L.or_run.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray, ct):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of one 128-bit counter under one 64-bit key."""
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox(_p(c, ctypes.c_uint32), _p(k, ctypes.c_uint32), _p(out, ctypes.c_uint32))
+    return out
+
+
+def threshold(K: float) -> int:
+    """floor(2^32 (1 - e^{-K})); 2^32 for K = inf; -1 for invalid K."""
+    t = lib().or_threshold(float(K))
+    return -1 if t == 2**64 - 1 else int(t)
+
+
+def state_of_draw(w: int, q: int) -> int:
+    return int(lib().or_state_of_draw(w, q))
+
+
+def newspin(seed: int, sweep: int, root: int, q: int) -> int:
+    return int(lib().or_newspin(seed, sweep, root, q))
+
+
+def initspin(seed: int, site: int, q: int) -> int:
+    return int(lib().or_initspin(seed, site, q))
+
+
+def bond_draws(seed: int, sweep: int, site: int):
+    wx = ctypes.c_uint32()
+    wy = ctypes.c_uint32()
+    lib().or_bond_draws(seed, sweep, site, ctypes.byref(wx), ctypes.byref(wy))
+    return int(wx.value), int(wy.value)
+
+
+def init_spins(L: int, q: int, seed: int, random_start: bool) -> np.ndarray:
+    s = np.zeros(L * L, dtype=np.uint8)
+    rc = lib().or_init(L, q, seed, 1 if random_start else 0, _p(s, ctypes.c_uint8))
+    if rc != 0:
+        raise ValueError("oracle init rejected its parameters")
+    return s.reshape(L, L)
+
+
+def observe(s: np.ndarray, q: int) -> np.ndarray:
+    """[n_unsat, 0, n_0..n_{q-1}] of a configuration (n_active is not defined here)."""
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    L = s.shape[0]
+    obs = np.zeros(2 + q, dtype=np.int64)
+    lib().or_observe(L, q, _p(s.reshape(-1), ctypes.c_uint8), _p(obs, ctypes.c_int64))
+    return obs
+
+
+def label(bx: np.ndarray, by: np.ndarray) -> np.ndarray:
+    """Minimum-site-index cluster labels of the graph of active bonds."""
+    L = bx.shape[0]
+    bx = np.ascontiguousarray(bx, dtype=np.uint8).reshape(-1)
+    by = np.ascontiguousarray(by, dtype=np.uint8).reshape(-1)
+    lab = np.zeros(L * L, dtype=np.uint32)
+    lib().or_label(L, _p(bx, ctypes.c_uint8), _p(by, ctypes.c_uint8), _p(lab, ctypes.c_uint32))
+    return lab.reshape(L, L)
+
+
+class OracleLattice:
+    """One L x L lattice stepped by the oracle, one sweep at a time.
+
+    ``sweep()`` returns the sweep's bonds (uint8 [L, L] per direction), labels
+    (uint32 [L, L]) and observables [n_unsat, n_active, n_0..n_{q-1}] of the
+    configuration after the flip; ``self.s`` holds the spins.
+    """
+
+    def __init__(self, L: int, q: int, K: float, seed: int, random_start: bool = True,
+                 spins: np.ndarray | None = None, sweep: int = 0):
+        self.L, self.q, self.K, self.seed = int(L), int(q), float(K), int(seed)
+        if spins is None:
+            self.s = init_spins(self.L, self.q, self.seed, random_start)
+        else:
+            self.s = np.ascontiguousarray(spins, dtype=np.uint8).reshape(self.L, self.L).copy()
+        self.t = int(sweep)
+        n = self.L * self.L
+        self.bx = np.zeros(n, dtype=np.uint8)
+        self.by = np.zeros(n, dtype=np.uint8)
+        self.lab = np.zeros(n, dtype=np.uint32)
+
+    def sweep(self) -> dict:
+        obs = np.zeros(2 + self.q, dtype=np.int64)
+        flat = self.s.reshape(-1)
+        rc = lib().or_sweep(self.L, self.q, self.K, self.seed, self.t, _p(flat, ctypes.c_uint8),
+                            _p(self.bx, ctypes.c_uint8), _p(self.by, ctypes.c_uint8),
+                            _p(self.lab, ctypes.c_uint32), _p(obs, ctypes.c_int64))
+        if rc != 0:
+            raise ValueError("oracle sweep rejected its parameters")
+        self.t += 1
+        L = self.L
+        return {"bx": self.bx.reshape(L, L).copy(), "by": self.by.reshape(L, L).copy(),
+                "labels": self.lab.reshape(L, L).copy(), "obs": obs}
+
+    def run(self, n: int) -> np.ndarray:
+        """n sweeps; returns the int64 observable rows [n, 2+q]."""
+        obs = np.zeros((n, 2 + self.q), dtype=np.int64)
+        flat = self.s.reshape(-1)
+        rc = lib().or_run(self.L, self.q, self.K, self.seed, self.t, n, _p(flat, ctypes.c_uint8),
+                          _p(obs.reshape(-1), ctypes.c_int64))
+        if rc != 0:
+            raise ValueError("oracle run failed")
+        self.t += n
+        return obs
+
+
+def pack_bonds(b: np.ndarray) -> np.ndarray:
+    """Pack a uint8 [L, L] bond plane into uint64 words, ceil(L/64) per row,
+    bit (x mod 64) of word x // 64 holding the bond of site x (padding bits 0)."""
+    L = b.shape[0]
+    W = (L + 63) // 64
+    padded = np.zeros((L, W * 64), dtype=np.uint8)
+    padded[:, :L] = b
+    bits = np.packbits(padded.reshape(L, W, 64), axis=-1, bitorder="little")  # [L, W, 8]
+    return bits.reshape(L, W * 8).view(np.uint64).reshape(L, W)
