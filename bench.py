@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the Swendsen-Wang sweep on one MI355X.
+
+One step = one full SW sweep (bonds, cluster labels, flip) of the 2D q-state
+Potts model including the measurement of energy and state counts ("update +
+measurement" of the paper's Table 1).  Default workload: q = 2 at the critical
+coupling K_c = ln(1 + sqrt 2), L = 16384 (2^28 sites), random start, synthetic.
+
+Prints one JSON line: spin flips per ns (L^2 x sweeps / time), the roofline of
+the dominant kernel (HIP-event time per launch against its algorithmic bytes),
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, vendor figure
+# algorithmic bytes per site of one launch (uint8 spins, uint32 labels, 2-bit bonds)
+KERNEL_BYTES_PER_SITE = {
+    "k_bond_label": 1.0 + 0.25 + 4.0,   # read spins, write bond planes, write labels
+    "k_flip": 4.0 + 1.0,                # read labels, write spins
+}
+SWEEP_BYTES_PER_SITE = 10.25
+PHASE_KERNELS = ["k_bond_label", "k_merge", "k_flip", "k_measure+k_bump"]
+
+
+def workloads():
+    from paper_1208_2080_amd import workloads as wl
+    return {
+        "L16384": dict(wl.PLAIN_16384),
+        "L4096": dict(wl.PLAIN_4096),
+        "L65536q2": dict(wl.HUGE_Q2),
+        "L65536q3": dict(wl.HUGE_Q3),
+        "L64": dict(wl.SMALL),
+    }
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for name in ("sw_kernels.hip", "sw_device.hpp", "sw_layout.hpp"):
+        with open(os.path.join(ROOT, "paper_1208_2080_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str, tile_rows: int):
+    """HBM bytes per launch from committed rocprofv3 PMC summaries, if they were
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_ty{tile_rows}_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                vals[k.strip()] = v.strip()
+    try:
+        if vals.get("kernel_source_sha256_16") != kernel_source_digest():
+            return None
+        scale = float(vals["copy_scale_bytes_per_kib"])
+        return (float(vals["fetch_kib_per_dispatch"]) + float(vals["write_kib_per_dispatch"])) * scale
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(cfg: dict) -> dict:
+    """The CPU oracle, single-threaded, on one sweep of the same lattice."""
+    import oracle
+    L = cfg["L"]
+    lat = oracle.OracleLattice(L, cfg["q"], cfg["K"], cfg["seed"], random_start=cfg["random_start"])
+    t0 = time.perf_counter()
+    lat.run(1)
+    dt = time.perf_counter() - t0
+    return {"value": L * L / (dt * 1e9), "unit": "spin flips/ns", "cores": 1, "kind": "oracle",
+            "sample": f"1 sweep of the same L={L} q={cfg['q']} lattice from its start (sweep 0), "
+                      f"{dt:.1f} s on 1 host core ({os.cpu_count()} visible)"}
+
+
+def copy_calibration(nbytes: int = 1 << 30):
+    """A plain device copy of known size, for scaling HBM byte counters."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000, help="timed sweeps")
+    ap.add_argument("--warmup", type=int, default=50, help="untimed sweeps first")
+    ap.add_argument("--workload", default="L16384", choices=sorted(workloads()))
+    ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--update-only", action="store_true", help="no measurement (Table 1 'update only')")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (reference for HBM byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sweep of one lattice runs on one MI355X); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1208_2080_amd import binding
+
+    cfg = workloads()[args.workload]
+    L, q, K = cfg["L"], cfg["q"], cfg["K"]
+    N = L * L
+    torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
+    lat = binding.Lattice(L, q, K, seed=cfg["seed"], random_start=cfg["random_start"],
+                          obs_capacity=0 if args.update_only else 1024, tile_rows=args.tile_rows)
+    print(f"# {args.workload}: L={L} q={q} K={K:.12f} ({N} sites), warmup {args.warmup}", file=sys.stderr,
+          flush=True)
+    lat.sweep(args.warmup)
+    torch.cuda.synchronize()
+
+    # timed region: exactly `steps` sweeps, HIP events around every kernel
+    phases = [0.0, 0.0, 0.0, 0.0]
+    chunk = 5000
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.steps:
+        n = min(chunk, args.steps - done)
+        ph = lat.sweep_profiled(n)
+        phases = [a + b for a, b in zip(phases, ph)]
+        done += n
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    print(f"# timed {args.steps} sweeps in {wall:.3f} s", file=sys.stderr, flush=True)
+
+    if not args.update_only:
+        obs = lat.measure(lat.sweeps_done - 1, 1)[0]
+        assert obs[2:].sum() == N, "observable counts do not sum to N"
+
+    value = N * args.steps / (wall * 1e9)
+    per_launch_ms = {PHASE_KERNELS[i]: phases[i] / args.steps for i in range(3)}
+    dominant = max(("k_bond_label", "k_flip"), key=lambda k: per_launch_ms[k])
+    ty = args.tile_rows or 64
+    alg_bytes = KERNEL_BYTES_PER_SITE[dominant] * N
+    achieved = alg_bytes / (per_launch_ms[dominant] * 1e-3) / 1e9
+    traffic = measured_traffic(dominant, args.workload, ty)
+    out = {
+        "metric": "spin flips/ns on 1 MI355X, q=2 at K_c, L=16384/65536; batched vs plain",
+        "value": value,
+        "unit": "spin flips/ns",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"SW sweep, 2D Potts L={L} q={q} K={K:.9f} periodic, "
+                               f"{'random' if cfg['random_start'] else 'cold'} start, "
+                               f"{'update only' if args.update_only else 'update + measurement'}",
+                   "L": L, "q": q, "K": K, "seed": cfg["seed"], "tile_rows": ty},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "alg_bytes_per_launch": alg_bytes,
+                     "avg_launch_ms": per_launch_ms[dominant]},
+        "phase_ms_per_sweep": {k: v for k, v in per_launch_ms.items()},
+        "sweep_roofline_frac": value * SWEEP_BYTES_PER_SITE / HBM_PEAK_GBS,
+    }
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        print("# timing the CPU oracle on one sweep", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,155 @@
+/*
+ * swmi -- Swendsen-Wang multi-cluster sweep of the 2D q-state Potts model on one
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The operation (Komura & Okabe, "Multi-GPU-based Swendsen-Wang multi-cluster
+ * algorithm for the simulation of two-dimensional q-state Potts model"):
+ *   Sec. 2, Eq. (1): H = -J sum_<ij> (delta(S_i, S_j) - 1) on an L x L square
+ *   lattice with periodic boundaries; one SW sweep = (1) activate bonds,
+ *   (2) label the clusters of active bonds, (3) set every cluster to a random
+ *   one of the q states.  The proper label of a cluster is its smallest label
+ *   (Sec. 2, Hoshen-Kopelman paragraph), so cluster roots are minimum site
+ *   indices.  Energy and magnetisation are measured after each sweep (Sec. 4,
+ *   Table 1, "update + measurement").
+ *
+ * Fixed conventions (readings where the paper is silent):
+ *   site index i = y*L + x; spins 0..q-1 (uint8); each site owns its bonds to
+ *   (x+1, y) and (x, y+1) (periodic), 2N bonds in all; an equal-spin bond is
+ *   active iff w < floor(2^32 (1 - e^{-K})), w a Philox4x32-10 draw keyed
+ *   key = (seed lo, seed hi), bond counter (i >> 1, 0, sweep, 0) with words
+ *   2(i&1) (+x) and 2(i&1)+1 (+y); the new state of a cluster with root r is
+ *   floor(w q / 2^32), w = word 0 of counter (r, 0, sweep, 1); a random start
+ *   uses word 0 of counter (i, 0, 0, 2) the same way.  Sweeps are numbered
+ *   0, 1, 2, ... from sw_init.
+ *
+ * Memory and streams: the caller owns the device workspace (one allocation of
+ * sw_workspace_bytes(), 256-byte aligned) and the HIP stream; both must stay
+ * alive until sw_destroy.  The library never allocates device memory.  A handle
+ * is bound to one stream and is not thread safe.  Host buffers are ordinary
+ * (pageable) host memory owned by the caller.
+ *
+ * Errors: every int function returns SW_OK (0) or a negative SW_E* code and
+ * never throws; sw_last_error() gives a message for the calling thread.
+ * Work is asynchronous on the stream: sw_sweep returns before the GPU is done,
+ * and a failure detected inside a kernel surfaces at the next call that
+ * synchronises (sw_measure, sw_read_*).
+ */
+#ifndef SWMI_SW_H
+#define SWMI_SW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SW_OK 0
+#define SW_EINVAL (-1)     /* bad argument: L < 2 or > 65536, q < 2 or > 255, K < 0 or NaN, ... */
+#define SW_ESPACE (-2)     /* workspace too small or not 256-byte aligned */
+#define SW_EHIP (-3)       /* HIP runtime error; text in sw_last_error() */
+#define SW_ESTATE (-4)     /* sweep counter would pass 2^32 - 1, or data not available */
+#define SW_ECONVERGE (-5)  /* a labelling loop hit its safety cap (a bug detector) */
+
+/* Parameters of one lattice. */
+typedef struct sw_params {
+    uint32_t L;            /* linear size, 2..65536 (N = L*L <= 2^32 sites) */
+    uint32_t q;            /* number of Potts states, 2..255 */
+    double K;              /* coupling J / k_B T, >= 0; +inf allowed (p = 1) */
+    uint64_t seed;         /* Philox key */
+    uint32_t init;         /* 0 = cold start (all spins 0), 1 = random start */
+    uint32_t obs_capacity; /* sweeps of observables kept in the device ring;
+                              0 = no measurement ("update only"), else >= 2 */
+    uint32_t tile_rows;    /* labelling tile height: 0 (default), 32, 64 or 128 */
+    uint32_t reserved;     /* must be 0 */
+} sw_params;
+
+typedef struct sw_lattice sw_lattice;
+typedef struct sw_batch sw_batch;
+
+/* Device bytes one lattice needs; 0 if the parameters are invalid. */
+size_t sw_workspace_bytes(const sw_params* p);
+
+/* Integer bond threshold floor(2^32 (1 - e^{-K})) in [0, 2^32] (bond
+ * probability of Sec. 2 step (1) as an integer test on a 32-bit draw). */
+int sw_threshold(const sw_params* p, uint64_t* thr);
+
+/* Carve the lattice out of dev_ws (device pointer, ws_bytes bytes) and write the
+ * initial spins on hip_stream (a hipStream_t; NULL = default stream).  *out
+ * receives a host-side handle owned by the library. */
+int sw_init(const sw_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, sw_lattice** out);
+
+/* Enqueue n_sweeps SW sweeps (Sec. 2 steps (1)-(3)) on the handle's stream,
+ * each followed by the measurement of energy and state counts when
+ * obs_capacity > 0.  Asynchronous. */
+int sw_sweep(sw_lattice* h, uint32_t n_sweeps);
+
+/* Observables of sweeps first .. first+n-1 (after each sweep's flip), copied
+ * into host_out as n rows of (2 + q) int64: [n_unsat, n_active, n_0, ...,
+ * n_{q-1}], where n_unsat = number of unsatisfied bonds (energy of Eq. (1) in
+ * units of J), n_active = bonds activated in that sweep, n_c = sites in state
+ * c.  Only the last obs_capacity sweeps since sw_init / sw_load_spins are
+ * kept.  Synchronises the stream. */
+int sw_measure(sw_lattice* h, uint32_t first, uint32_t n, int64_t* host_out);
+
+/* sw_sweep with timing: HIP events are recorded on the handle's stream around
+ * every kernel launch; the call then synchronises and writes the summed device
+ * time of each phase, in milliseconds, into phase_ms[4]: [0] bonds + tile
+ * labels (+ measurement of the incoming configuration), [1] tile-edge merge,
+ * [2] flip, [3] final measurement and counter update.  The results are the same
+ * as sw_sweep's. */
+int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms);
+
+/* Number of sweeps done since sw_init (the index of the next sweep). */
+int sw_sweeps_done(const sw_lattice* h, uint32_t* out);
+
+/* Current spins, N bytes row-major.  Synchronises the stream. */
+int sw_read_spins(sw_lattice* h, uint8_t* host_out);
+
+/* Replace the spins (N bytes, each < q) and set the sweep counter to `sweep`
+ * (checkpoint / resume).  Observables before `sweep` are dropped. */
+int sw_load_spins(sw_lattice* h, const uint8_t* host_in, uint32_t sweep);
+
+/* Cluster labels of the last sweep: N uint32, label[i] = smallest site index
+ * of i's cluster.  Needs at least one sweep since init / load.  Synchronises. */
+int sw_read_labels(sw_lattice* h, uint32_t* host_out);
+
+/* Active bonds of the last sweep as two bit planes (+x, then +y), each L rows
+ * of ceil(L/64) uint64 words; bit (x mod 64) of word x/64 of row y is the bond
+ * of site (x, y); padding bits are 0.  2 * L * ceil(L/64) words.  Synchronises. */
+int sw_read_bonds(sw_lattice* h, uint64_t* host_out);
+
+/* Release the handle (not the workspace or the stream). */
+int sw_destroy(sw_lattice* h);
+
+/* ---------------------------------------------------------------- batched
+ * Many independent lattices ("replicas") of uneven L, q and K swept by the
+ * same kernels in one launch per phase.  Replica r behaves bit for bit like a
+ * plain lattice with params[r] (same random draws: nothing but the replica's
+ * own seed and sweep index keys them). */
+
+/* Device bytes for n replicas. */
+int sw_batch_workspace_bytes(const sw_params* params, uint32_t n, size_t* bytes);
+
+int sw_batch_init(const sw_params* params, uint32_t n, void* dev_ws, size_t ws_bytes,
+                  void* hip_stream, sw_batch** out);
+
+/* Sweep replica r n_sweeps[r] times (0 = leave it alone); asynchronous. */
+int sw_batch_sweep(sw_batch* b, const uint32_t* n_sweeps);
+
+/* Same sweep count for every replica, n times over (captured as a HIP graph). */
+int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps);
+
+int sw_batch_measure(sw_batch* b, uint32_t replica, uint32_t first, uint32_t n, int64_t* host_out);
+int sw_batch_read_spins(sw_batch* b, uint32_t replica, uint8_t* host_out);
+int sw_batch_sweeps_done(const sw_batch* b, uint32_t replica, uint32_t* out);
+int sw_batch_destroy(sw_batch* b);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* sw_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWMI_SW_H */

@@ -1,0 +1,266 @@
+"""Python binding of the C ABI in ``include/sw.h`` (argument marshalling only).
+
+Every step of a sweep runs in the HIP kernels of ``libswmi.so``; this module
+only allocates the device workspace as a torch tensor, hands torch's HIP stream
+to the library and copies results into numpy arrays.  There is no fallback: if
+the library is missing or fails to load, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libswmi.so")
+
+SW_OK, SW_EINVAL, SW_ESPACE, SW_EHIP, SW_ESTATE, SW_ECONVERGE = 0, -1, -2, -3, -4, -5
+
+
+class SwError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"swmi error {code}: {msg}")
+        self.code = code
+
+
+class SwParams(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("q", ctypes.c_uint32), ("K", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("init", ctypes.c_uint32), ("obs_capacity", ctypes.c_uint32),
+                ("tile_rows", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+# (name, restype, argtypes) of every function declared in include/sw.h
+_VP = ctypes.c_void_p
+_PP = ctypes.POINTER(SwParams)
+_U32 = ctypes.c_uint32
+SIGNATURES = [
+    ("sw_workspace_bytes", ctypes.c_size_t, [_PP]),
+    ("sw_threshold", ctypes.c_int, [_PP, ctypes.POINTER(ctypes.c_uint64)]),
+    ("sw_init", ctypes.c_int, [_PP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    ("sw_sweep", ctypes.c_int, [_VP, _U32]),
+    ("sw_measure", ctypes.c_int, [_VP, _U32, _U32, _VP]),
+    ("sw_sweep_profiled", ctypes.c_int, [_VP, _U32, ctypes.POINTER(ctypes.c_double)]),
+    ("sw_sweeps_done", ctypes.c_int, [_VP, ctypes.POINTER(_U32)]),
+    ("sw_read_spins", ctypes.c_int, [_VP, _VP]),
+    ("sw_load_spins", ctypes.c_int, [_VP, _VP, _U32]),
+    ("sw_read_labels", ctypes.c_int, [_VP, _VP]),
+    ("sw_read_bonds", ctypes.c_int, [_VP, _VP]),
+    ("sw_destroy", ctypes.c_int, [_VP]),
+    ("sw_batch_workspace_bytes", ctypes.c_int, [_PP, _U32, ctypes.POINTER(ctypes.c_size_t)]),
+    ("sw_batch_init", ctypes.c_int, [_PP, _U32, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    ("sw_batch_sweep", ctypes.c_int, [_VP, _VP]),
+    ("sw_batch_sweep_all", ctypes.c_int, [_VP, _U32]),
+    ("sw_batch_measure", ctypes.c_int, [_VP, _U32, _U32, _U32, _VP]),
+    ("sw_batch_read_spins", ctypes.c_int, [_VP, _U32, _VP]),
+    ("sw_batch_sweeps_done", ctypes.c_int, [_VP, _U32, ctypes.POINTER(_U32)]),
+    ("sw_batch_destroy", ctypes.c_int, [_VP]),
+    ("sw_last_error", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+def lib():
+    """Load ``libswmi.so`` (after torch, so both share torch's HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1208_2080_amd.build.build()")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        runtimes = set()
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    runtimes.add(os.path.realpath(line.split()[-1]))
+        if len(runtimes) > 1:
+            raise RuntimeError(f"two HIP runtimes are loaded ({sorted(runtimes)}); import torch first")
+        _lib = handle
+    return _lib
+
+
+def _check(rc: int):
+    if rc != SW_OK:
+        raise SwError(rc, lib().sw_last_error().decode())
+
+
+def make_params(L: int, q: int, K: float, seed: int = 1, random_start: bool = True,
+                obs_capacity: int = 2, tile_rows: int = 0) -> SwParams:
+    return SwParams(int(L), int(q), float(K), int(seed), 1 if random_start else 0, int(obs_capacity),
+                    int(tile_rows), 0)
+
+
+def threshold(K: float) -> int:
+    thr = ctypes.c_uint64()
+    _check(lib().sw_threshold(ctypes.byref(make_params(2, 2, K)), ctypes.byref(thr)))
+    return int(thr.value)
+
+
+def workspace_bytes(L: int, q: int, obs_capacity: int = 2, tile_rows: int = 0) -> int:
+    p = make_params(L, q, 1.0, obs_capacity=obs_capacity, tile_rows=tile_rows)
+    n = lib().sw_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        raise SwError(SW_EINVAL, lib().sw_last_error().decode())
+    return int(n)
+
+
+def _stream_handle(stream) -> int:
+    return int(stream.cuda_stream)
+
+
+def derived(row: np.ndarray, L: int, q: int) -> dict:
+    """Energy per site and order parameter from one int64 observable row
+    [n_unsat, n_active, n_0, ..., n_{q-1}] (host FP64)."""
+    N = float(L) * L
+    counts = row[2:2 + q].astype(np.float64)
+    out = {"e": float(row[0]) / N, "m": (q * counts.max() / N - 1.0) / (q - 1)}
+    if q == 2:
+        out["M"] = float(row[2] - row[3])
+    return out
+
+
+class Lattice:
+    """One L x L lattice resident on the GPU, swept by the HIP kernels."""
+
+    def __init__(self, L: int, q: int, K: float, seed: int = 1, random_start: bool = True,
+                 obs_capacity: int = 1024, tile_rows: int = 0, device=None, stream=None):
+        self.L, self.q, self.K, self.seed = int(L), int(q), float(K), int(seed)
+        self.obs_capacity = int(obs_capacity)
+        self.params = make_params(L, q, K, seed, random_start, obs_capacity, tile_rows)
+        nbytes = lib().sw_workspace_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            raise SwError(SW_EINVAL, lib().sw_last_error().decode())
+        self.device = torch.device("cuda", 0) if device is None else torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        _check(lib().sw_init(ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                             ctypes.c_void_p(_stream_handle(self.stream)), ctypes.byref(self._h)))
+
+    @property
+    def N(self) -> int:
+        return self.L * self.L
+
+    @property
+    def W(self) -> int:
+        return (self.L + 63) // 64
+
+    def sweep(self, n: int = 1):
+        _check(lib().sw_sweep(self._h, int(n)))
+
+    def sweep_profiled(self, n: int) -> np.ndarray:
+        """n sweeps with HIP events around every kernel; returns the summed device
+        milliseconds of [bonds + tile labels, merge, flip, final measurement]."""
+        out = (ctypes.c_double * 4)()
+        _check(lib().sw_sweep_profiled(self._h, int(n), out))
+        return np.array(out[:], dtype=np.float64)
+
+    @property
+    def sweeps_done(self) -> int:
+        v = ctypes.c_uint32()
+        _check(lib().sw_sweeps_done(self._h, ctypes.byref(v)))
+        return int(v.value)
+
+    def measure(self, first: int, n: int) -> np.ndarray:
+        out = np.zeros((n, 2 + self.q), dtype=np.int64)
+        _check(lib().sw_measure(self._h, int(first), int(n), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def spins(self) -> np.ndarray:
+        out = np.empty((self.L, self.L), dtype=np.uint8)
+        _check(lib().sw_read_spins(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def load_spins(self, s: np.ndarray, sweep: int):
+        s = np.ascontiguousarray(s, dtype=np.uint8).reshape(self.L, self.L)
+        _check(lib().sw_load_spins(self._h, s.ctypes.data_as(ctypes.c_void_p), int(sweep)))
+
+    def labels(self) -> np.ndarray:
+        out = np.empty((self.L, self.L), dtype=np.uint32)
+        _check(lib().sw_read_labels(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def bonds(self):
+        """(+x plane, +y plane), each uint64 [L, ceil(L/64)]."""
+        out = np.empty((2, self.L, self.W), dtype=np.uint64)
+        _check(lib().sw_read_bonds(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out[0], out[1]
+
+    def close(self):
+        if self._h:
+            lib().sw_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent replicas of uneven L, q and K swept together, one launch per phase."""
+
+    def __init__(self, replicas, obs_capacity: int = 64, tile_rows: int = 0, device=None, stream=None):
+        self.replicas = [dict(r) for r in replicas]
+        n = len(self.replicas)
+        arr = (SwParams * n)()
+        for i, r in enumerate(self.replicas):
+            arr[i] = make_params(r["L"], r["q"], r["K"], r["seed"], r.get("random_start", True),
+                                 r.get("obs_capacity", obs_capacity), tile_rows)
+        self.params = arr
+        nbytes = ctypes.c_size_t()
+        _check(lib().sw_batch_workspace_bytes(arr, n, ctypes.byref(nbytes)))
+        self.device = torch.device("cuda", 0) if device is None else torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        _check(lib().sw_batch_init(arr, n, ctypes.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                   ctypes.c_void_p(_stream_handle(self.stream)), ctypes.byref(self._h)))
+
+    def __len__(self):
+        return len(self.replicas)
+
+    def sweep(self, n_each):
+        v = np.ascontiguousarray(n_each, dtype=np.uint32)
+        assert v.size == len(self)
+        _check(lib().sw_batch_sweep(self._h, v.ctypes.data_as(ctypes.c_void_p)))
+
+    def sweep_all(self, n: int):
+        _check(lib().sw_batch_sweep_all(self._h, int(n)))
+
+    def sweeps_done(self, r: int) -> int:
+        v = ctypes.c_uint32()
+        _check(lib().sw_batch_sweeps_done(self._h, int(r), ctypes.byref(v)))
+        return int(v.value)
+
+    def measure(self, r: int, first: int, n: int) -> np.ndarray:
+        q = self.replicas[r]["q"]
+        out = np.zeros((n, 2 + q), dtype=np.int64)
+        _check(lib().sw_batch_measure(self._h, int(r), int(first), int(n), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def spins(self, r: int) -> np.ndarray:
+        L = self.replicas[r]["L"]
+        out = np.empty((L, L), dtype=np.uint8)
+        _check(lib().sw_batch_read_spins(self._h, int(r), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def close(self):
+        if self._h:
+            lib().sw_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

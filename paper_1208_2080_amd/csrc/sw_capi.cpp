@@ -1,0 +1,734 @@
+// C ABI of the SW sweep library: handle management, workspace carving, the
+// fixed per-sweep kernel schedule and error mapping.  The library never
+// allocates device memory; every device byte comes from the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sw.h"
+#include "sw_kernels.hpp"
+#include "sw_layout.hpp"
+
+using namespace swmi;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(SW_EHIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+constexpr uint32_t DEFAULT_TY = 64;
+
+// Validate parameters; on success fill the derived geometry.
+struct Geometry {
+    uint32_t L, q, W, ty, ntx, nty, ntiles, cap;
+    size_t N;
+    uint64_t thr;
+};
+
+uint64_t threshold_of(double K)
+{
+    if (std::isinf(K)) return 1ull << 32;
+    const double p = -std::expm1(-K);    // bond probability 1 - e^{-K}
+    return (uint64_t)std::floor(std::ldexp(p, 32));
+}
+
+int check_params(const sw_params* p, Geometry* g)
+{
+    if (!p) return fail(SW_EINVAL, "params is NULL");
+    if (p->L < 2 || p->L > 65536) return fail(SW_EINVAL, "L = %u outside 2..65536", p->L);
+    if (p->q < 2 || p->q > 255) return fail(SW_EINVAL, "q = %u outside 2..255", p->q);
+    if (std::isnan(p->K) || p->K < 0) return fail(SW_EINVAL, "K must be >= 0 (got %g)", p->K);
+    if (p->init > 1) return fail(SW_EINVAL, "init must be 0 (cold) or 1 (random)");
+    if (p->obs_capacity == 1) return fail(SW_EINVAL, "obs_capacity must be 0 or >= 2");
+    if (p->obs_capacity > (1u << 28)) return fail(SW_EINVAL, "obs_capacity too large");
+    const uint32_t ty = p->tile_rows ? p->tile_rows : DEFAULT_TY;
+    if (ty != 32 && ty != 64 && ty != 128) return fail(SW_EINVAL, "tile_rows must be 0, 32, 64 or 128");
+    if (p->reserved != 0) return fail(SW_EINVAL, "reserved must be 0");
+    g->L = p->L;
+    g->q = p->q;
+    g->W = (p->L + 63) / 64;
+    g->ty = ty;
+    g->ntx = (p->L + TX - 1) / TX;
+    g->nty = (p->L + ty - 1) / ty;
+    g->ntiles = g->ntx * g->nty;
+    g->cap = p->obs_capacity;
+    g->N = (size_t)p->L * p->L;
+    g->thr = threshold_of(p->K);
+    return SW_OK;
+}
+
+// The ring keeps one slot more than the sweeps it reports: the slot of the
+// next sweep is cleared ahead of time by the flip kernel.
+inline uint32_t ring_slots(const Geometry& g) { return g.cap ? g.cap + 1 : 0; }
+
+// Byte offsets of one lattice's arrays inside its slice of the workspace.
+struct Carve {
+    size_t state, desc, spins, lab, bonds, edges, ring, total;
+};
+
+Carve carve(const Geometry& g)
+{
+    Carve c{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    c.state = take(sizeof(DevState));
+    c.desc = take(sizeof(LatDesc));
+    c.spins = take(g.N);
+    c.lab = take(g.N * 4);
+    c.bonds = take((size_t)2 * g.L * g.W * 8);
+    c.edges = take((size_t)g.ntiles * edge_words(g.ty) * 4);
+    c.ring = take((size_t)ring_slots(g) * NCOPY * (g.q + 1) * 8);
+    c.total = off;
+    return c;
+}
+
+// Multiply-high division by L (Granlund & Montgomery): l = ceil(log2 L).
+void division_magic(uint32_t L, uint32_t* magic, uint32_t* shift)
+{
+    uint32_t l = 0;
+    while ((1ull << l) < L) ++l;
+    *magic = (uint32_t)((((1ull << l) - L) << 32) / L + 1);
+    *shift = l - 1;
+}
+
+bool division_ok(uint32_t L, uint32_t magic, uint32_t shift)
+{
+    const uint32_t probes[] = {0u, 1u, L - 1, L, L + 1, 2 * L - 1, 0x7FFFFFFFu, 0x80000000u,
+                               0xFFFFFFFEu, 0xFFFFFFFFu, (uint32_t)((uint64_t)L * L - 1), 123456789u};
+    for (uint32_t n : probes) {
+        const uint32_t t = (uint32_t)(((uint64_t)magic * n) >> 32);
+        if (((t + ((n - t) >> 1)) >> shift) != n / L) return false;
+    }
+    return true;
+}
+
+LatDesc make_desc(const Geometry& g, const sw_params* p, char* base, const Carve& c)
+{
+    LatDesc d{};
+    DevState* st = reinterpret_cast<DevState*>(base + c.state);
+    d.s = reinterpret_cast<uint8_t*>(base + c.spins);
+    d.lab = reinterpret_cast<uint32_t*>(base + c.lab);
+    d.bonds = reinterpret_cast<uint64_t*>(base + c.bonds);
+    d.edges = reinterpret_cast<uint32_t*>(base + c.edges);
+    d.ring = g.cap ? reinterpret_cast<int64_t*>(base + c.ring) : nullptr;
+    d.counter = &st->counter;
+    d.err = &st->err;
+    d.L = g.L;
+    d.q = g.q;
+    d.W = g.W;
+    d.ntx = g.ntx;
+    d.nty = g.nty;
+    d.ntiles = g.ntiles;
+    d.cap = ring_slots(g);
+    d.thr_nz = g.thr != 0;
+    d.thr_m1 = g.thr ? (uint32_t)(g.thr - 1) : 0u;
+    d.key0 = (uint32_t)p->seed;
+    d.key1 = (uint32_t)(p->seed >> 32);
+    division_magic(g.L, &d.magic, &d.shift);
+    return d;
+}
+
+}  // namespace
+
+// One lattice: host-side view of its slice of the workspace.
+struct sw_lattice {
+    sw_params p;
+    Geometry g;
+    Carve c;
+    char* base;
+    LatDesc desc;            // host copy of the descriptor
+    LatDesc* d_desc;         // device copy (read by every kernel)
+    hipStream_t stream;
+    uint32_t done;           // sweeps done since init (index of the next sweep)
+    uint32_t first_obs;      // first sweep whose observables exist
+    bool have_sweep;         // labels and bonds of a sweep are in place
+};
+
+namespace {
+
+int check_device_error(const LatDesc& d, hipStream_t s)
+{
+    uint32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, d.err, sizeof err, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (err) return fail(SW_ECONVERGE, "a labelling loop hit its safety cap");
+    return SW_OK;
+}
+
+// Sum the NCOPY partial copies of ring records [first, first+n) into rows of
+// (2 + q) int64: n_unsat, n_active, n_0..n_{q-1}.
+int read_ring(const LatDesc& d, size_t N, hipStream_t s, uint32_t first, uint32_t n, int64_t* out)
+{
+    const uint32_t R = d.q + 1;
+    std::vector<int64_t> buf((size_t)NCOPY * R);
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint32_t t = first + k;
+        const int64_t* src = d.ring + (size_t)(t % d.cap) * NCOPY * R;
+        HIP_TRY(hipMemcpyAsync(buf.data(), src, buf.size() * 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        int64_t* row = out + (size_t)k * (2 + d.q);
+        std::memset(row, 0, (2 + d.q) * 8);
+        for (uint32_t cpy = 0; cpy < NCOPY; ++cpy) {
+            const int64_t* rec = buf.data() + (size_t)cpy * R;
+            row[0] += rec[0];
+            row[1] += rec[1];
+            for (uint32_t c = 1; c < d.q; ++c) row[2 + c] += rec[1 + c];
+        }
+        int64_t rest = 0;
+        for (uint32_t c = 1; c < d.q; ++c) rest += row[2 + c];
+        row[2] = (int64_t)N - rest;
+    }
+    return SW_OK;
+}
+
+// The fixed schedule of n sweeps on one Work description.  With ev (3n + 2
+// events) an event is recorded before the first launch and after every phase.
+int enqueue_sweeps(const Work& w, uint32_t n, bool measure, const LatDesc* descs, uint32_t count,
+                   const uint32_t* n_each, hipEvent_t* ev = nullptr)
+{
+    if (ev) HIP_TRY(hipEventRecord(ev[0], w.stream));
+    for (uint32_t k = 0; k < n; ++k) {
+        HIP_TRY(launch_bond_label(w, k, (measure && k > 0) ? 1u : 0u));
+        if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 1], w.stream));
+        HIP_TRY(launch_merge(w));
+        if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 2], w.stream));
+        HIP_TRY(launch_flip(w, k));
+        if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 3], w.stream));
+    }
+    if (measure) HIP_TRY(launch_measure(w, n - 1));
+    HIP_TRY(launch_bump(descs, count, n_each, n, w.stream));
+    if (ev) HIP_TRY(hipEventRecord(ev[3 * n + 1], w.stream));
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* sw_last_error(void) { return g_err.c_str(); }
+
+size_t sw_workspace_bytes(const sw_params* p)
+{
+    Geometry g;
+    if (check_params(p, &g) != SW_OK) return 0;
+    return carve(g).total;
+}
+
+int sw_threshold(const sw_params* p, uint64_t* thr)
+{
+    if (!p || !thr) return fail(SW_EINVAL, "NULL argument");
+    if (std::isnan(p->K) || p->K < 0) return fail(SW_EINVAL, "K must be >= 0 (got %g)", p->K);
+    *thr = threshold_of(p->K);
+    return SW_OK;
+}
+
+int sw_init(const sw_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, sw_lattice** out)
+{
+    if (!out) return fail(SW_EINVAL, "out is NULL");
+    *out = nullptr;
+    Geometry g;
+    int rc = check_params(p, &g);
+    if (rc) return rc;
+    const Carve c = carve(g);
+    if (!dev_ws || ((uintptr_t)dev_ws % ALIGN) != 0)
+        return fail(SW_ESPACE, "workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < c.total) return fail(SW_ESPACE, "workspace has %zu bytes, needs %zu", ws_bytes, c.total);
+    sw_lattice* h = new (std::nothrow) sw_lattice();
+    if (!h) return fail(SW_EINVAL, "out of host memory");
+    h->p = *p;
+    h->g = g;
+    h->c = c;
+    h->base = static_cast<char*>(dev_ws);
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->desc = make_desc(g, p, h->base, c);
+    if (!division_ok(g.L, h->desc.magic, h->desc.shift)) {
+        delete h;
+        return fail(SW_EINVAL, "internal: division by L self-check failed");
+    }
+    h->d_desc = reinterpret_cast<LatDesc*>(h->base + c.desc);
+    auto run = [&]() -> int {
+        HIP_TRY(hipMemsetAsync(h->base + c.state, 0, sizeof(DevState), h->stream));
+        HIP_TRY(hipMemcpyAsync(h->d_desc, &h->desc, sizeof(LatDesc), hipMemcpyHostToDevice, h->stream));
+        if (g.cap) HIP_TRY(hipMemsetAsync(h->base + c.ring, 0, (size_t)ring_slots(g) * NCOPY * (g.q + 1) * 8, h->stream));
+        if (p->init) HIP_TRY(launch_init(h->d_desc, 0, g.N, 1u, h->stream));
+        else HIP_TRY(hipMemsetAsync(h->desc.s, 0, g.N, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        return SW_OK;
+    };
+    rc = run();
+    if (rc) {
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return SW_OK;
+}
+
+int sw_sweep(sw_lattice* h, uint32_t n_sweeps)
+{
+    if (!h) return fail(SW_EINVAL, "handle is NULL");
+    if (n_sweeps == 0) return SW_OK;
+    if ((uint64_t)h->done + n_sweeps > 0xFFFFFFFFull) return fail(SW_ESTATE, "sweep counter would overflow");
+    const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream};
+    const int rc = enqueue_sweeps(w, n_sweeps, h->g.cap != 0, h->d_desc, 1, nullptr);
+    if (rc) return rc;
+    h->done += n_sweeps;
+    h->have_sweep = true;
+    return SW_OK;
+}
+
+int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms)
+{
+    if (!h || !phase_ms) return fail(SW_EINVAL, "NULL argument");
+    for (int i = 0; i < 4; ++i) phase_ms[i] = 0.0;
+    if (n_sweeps == 0) return SW_OK;
+    if ((uint64_t)h->done + n_sweeps > 0xFFFFFFFFull) return fail(SW_ESTATE, "sweep counter would overflow");
+    if (n_sweeps > (1u << 20)) return fail(SW_EINVAL, "profile at most 2^20 sweeps per call");
+    std::vector<hipEvent_t> ev(3 * (size_t)n_sweeps + 2, nullptr);
+    int rc = SW_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            rc = fail(SW_EHIP, "hipEventCreate failed");
+            break;
+        }
+    const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream};
+    if (rc == SW_OK) rc = enqueue_sweeps(w, n_sweeps, h->g.cap != 0, h->d_desc, 1, nullptr, ev.data());
+    if (rc == SW_OK) {
+        h->done += n_sweeps;
+        h->have_sweep = true;
+        if (hipEventSynchronize(ev.back()) != hipSuccess) rc = fail(SW_EHIP, "hipEventSynchronize failed");
+    }
+    for (uint32_t k = 0; rc == SW_OK && k < n_sweeps; ++k) {
+        for (int ph = 0; ph < 3; ++ph) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev[3 * k + ph], ev[3 * k + ph + 1]) != hipSuccess) {
+                rc = fail(SW_EHIP, "hipEventElapsedTime failed");
+                break;
+            }
+            phase_ms[ph] += ms;
+        }
+    }
+    if (rc == SW_OK) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[3 * (size_t)n_sweeps], ev.back()) != hipSuccess)
+            rc = fail(SW_EHIP, "hipEventElapsedTime failed");
+        phase_ms[3] = ms;
+    }
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc == SW_OK) rc = check_device_error(h->desc, h->stream);
+    return rc;
+}
+
+int sw_sweeps_done(const sw_lattice* h, uint32_t* out)
+{
+    if (!h || !out) return fail(SW_EINVAL, "NULL argument");
+    *out = h->done;
+    return SW_OK;
+}
+
+int sw_measure(sw_lattice* h, uint32_t first, uint32_t n, int64_t* host_out)
+{
+    if (!h || (!host_out && n)) return fail(SW_EINVAL, "NULL argument");
+    if (h->g.cap == 0) return fail(SW_ESTATE, "lattice was created with obs_capacity = 0");
+    const uint64_t end = (uint64_t)first + n;
+    const uint64_t lo = std::max<uint64_t>(h->first_obs, h->done > h->g.cap ? h->done - h->g.cap : 0);
+    if (first < lo || end > h->done)
+        return fail(SW_ESTATE, "sweeps [%u, %llu) not available (have [%llu, %u))", first,
+                    (unsigned long long)end, (unsigned long long)lo, h->done);
+    int rc = check_device_error(h->desc, h->stream);
+    if (rc) return rc;
+    return read_ring(h->desc, h->g.N, h->stream, first, n, host_out);
+}
+
+int sw_read_spins(sw_lattice* h, uint8_t* host_out)
+{
+    if (!h || !host_out) return fail(SW_EINVAL, "NULL argument");
+    HIP_TRY(hipMemcpyAsync(host_out, h->desc.s, h->g.N, hipMemcpyDeviceToHost, h->stream));
+    return check_device_error(h->desc, h->stream);
+}
+
+int sw_load_spins(sw_lattice* h, const uint8_t* host_in, uint32_t sweep)
+{
+    if (!h || !host_in) return fail(SW_EINVAL, "NULL argument");
+    for (size_t i = 0; i < h->g.N; ++i)
+        if (host_in[i] >= h->g.q) return fail(SW_EINVAL, "spin %u at site %zu is not below q", host_in[i], i);
+    HIP_TRY(hipMemcpyAsync(h->desc.s, host_in, h->g.N, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->desc.counter, &sweep, sizeof sweep, hipMemcpyHostToDevice, h->stream));
+    if (h->g.cap)
+        HIP_TRY(hipMemsetAsync(h->desc.ring, 0, (size_t)ring_slots(h->g) * NCOPY * (h->g.q + 1) * 8, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->done = sweep;
+    h->first_obs = sweep;
+    h->have_sweep = false;
+    return SW_OK;
+}
+
+int sw_read_labels(sw_lattice* h, uint32_t* host_out)
+{
+    if (!h || !host_out) return fail(SW_EINVAL, "NULL argument");
+    if (!h->have_sweep) return fail(SW_ESTATE, "no sweep since init / load");
+    HIP_TRY(launch_resolve(h->d_desc, 0, h->g.N, h->stream));
+    HIP_TRY(hipMemcpyAsync(host_out, h->desc.lab, h->g.N * 4, hipMemcpyDeviceToHost, h->stream));
+    return check_device_error(h->desc, h->stream);
+}
+
+int sw_read_bonds(sw_lattice* h, uint64_t* host_out)
+{
+    if (!h || !host_out) return fail(SW_EINVAL, "NULL argument");
+    if (!h->have_sweep) return fail(SW_ESTATE, "no sweep since init / load");
+    HIP_TRY(hipMemcpyAsync(host_out, h->desc.bonds, (size_t)2 * h->g.L * h->g.W * 8, hipMemcpyDeviceToHost,
+                           h->stream));
+    return check_device_error(h->desc, h->stream);
+}
+
+int sw_destroy(sw_lattice* h)
+{
+    delete h;
+    return SW_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batched
+// Replicas live one after another in the workspace, each laid out like a plain
+// lattice; a header in front holds the descriptor table, the work map (tile
+// list of the replicas being swept, largest sweep count first) and per-replica
+// sweep counts.
+struct sw_batch {
+    uint32_t n;
+    uint32_t ty;
+    hipStream_t stream;
+    char* base;
+    std::vector<sw_params> p;
+    std::vector<Geometry> g;
+    std::vector<size_t> off;        // byte offset of replica r's slice
+    std::vector<Carve> c;
+    std::vector<LatDesc> desc;
+    std::vector<uint32_t> done, first_obs;
+    LatDesc* d_descs;
+    WorkItem* d_map;
+    uint32_t* d_n;
+    size_t total_tiles;
+    std::vector<WorkItem> h_map;    // host copy of the last uploaded map
+    std::vector<uint32_t> h_n;
+    std::vector<uint32_t> map_order;  // replica order of the uploaded map
+    std::map<uint32_t, hipGraphExec_t> graphs;   // sweep_all graphs by sweep count
+};
+
+namespace {
+
+struct BatchLayout {
+    size_t descs, map, nvec, header;
+    std::vector<size_t> off;
+    std::vector<Geometry> g;
+    std::vector<Carve> c;
+    size_t total_tiles, total;
+    uint32_t ty;
+};
+
+int batch_layout(const sw_params* params, uint32_t n, BatchLayout* out)
+{
+    if (!params || n == 0) return fail(SW_EINVAL, "need at least one replica");
+    BatchLayout b{};
+    b.g.resize(n);
+    b.c.resize(n);
+    b.off.resize(n);
+    b.total_tiles = 0;
+    for (uint32_t r = 0; r < n; ++r) {
+        int rc = check_params(&params[r], &b.g[r]);
+        if (rc) return fail(rc, "replica %u: %s", r, g_err.c_str());
+        if (r && b.g[r].ty != b.g[0].ty) return fail(SW_EINVAL, "all replicas need the same tile_rows");
+        b.c[r] = carve(b.g[r]);
+        b.total_tiles += b.g[r].ntiles;
+    }
+    if (b.total_tiles >= 0xFFFFFFFFull) return fail(SW_EINVAL, "too many tiles in one batch");
+    b.ty = b.g[0].ty;
+    size_t off = 0;
+    b.descs = off;
+    off = align_up(off + sizeof(LatDesc) * n);
+    b.map = off;
+    off = align_up(off + sizeof(WorkItem) * b.total_tiles);
+    b.nvec = off;
+    off = align_up(off + sizeof(uint32_t) * n);
+    b.header = off;
+    for (uint32_t r = 0; r < n; ++r) {
+        b.off[r] = off;
+        off = align_up(off + b.c[r].total);
+    }
+    b.total = off;
+    *out = std::move(b);
+    return SW_OK;
+}
+
+// Upload the tile list of the replicas with n_each[r] > 0, largest count first,
+// so that the replicas still sweeping at step k are a prefix of the list.
+// Returns, through prefix[k], the number of work items active at step k.
+int upload_map(sw_batch* b, const uint32_t* n_each, uint32_t kmax, std::vector<uint32_t>* prefix)
+{
+    std::vector<uint32_t> order;
+    for (uint32_t r = 0; r < b->n; ++r)
+        if (n_each[r]) order.push_back(r);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) { return n_each[a] > n_each[c]; });
+    if (order != b->map_order || b->h_map.empty()) {
+        b->h_map.clear();
+        for (uint32_t r : order)
+            for (uint32_t t = 0; t < b->g[r].ntiles; ++t) b->h_map.push_back({r, t});
+        if (!b->h_map.empty())
+            HIP_TRY(hipMemcpyAsync(b->d_map, b->h_map.data(), b->h_map.size() * sizeof(WorkItem),
+                                   hipMemcpyHostToDevice, b->stream));
+        b->map_order = order;
+    }
+    prefix->assign(kmax, 0);
+    size_t acc = 0;
+    // replicas sorted by count descending: at step k the active ones are those with n > k
+    std::vector<size_t> ends;
+    for (uint32_t r : order) {
+        acc += b->g[r].ntiles;
+        ends.push_back(acc);
+    }
+    for (uint32_t k = 0; k < kmax; ++k) {
+        size_t m = 0;
+        for (size_t i = 0; i < order.size(); ++i)
+            if (n_each[order[i]] > k) m = ends[i];
+        (*prefix)[k] = (uint32_t)m;
+    }
+    return SW_OK;
+}
+
+int batch_enqueue(sw_batch* b, const uint32_t* n_each)
+{
+    uint32_t kmax = 0;
+    for (uint32_t r = 0; r < b->n; ++r) kmax = std::max(kmax, n_each[r]);
+    if (kmax == 0) return SW_OK;
+    std::vector<uint32_t> prefix;
+    int rc = upload_map(b, n_each, kmax, &prefix);
+    if (rc) return rc;
+    b->h_n.assign(n_each, n_each + b->n);
+    HIP_TRY(hipMemcpyAsync(b->d_n, b->h_n.data(), b->n * sizeof(uint32_t), hipMemcpyHostToDevice, b->stream));
+    for (uint32_t k = 0; k < kmax; ++k) {
+        const Work w{b->d_descs, b->d_map, prefix[k], b->ty, b->stream};
+        HIP_TRY(launch_bond_label(w, k, k > 0 ? 1u : 0u));
+        HIP_TRY(launch_merge(w));
+        HIP_TRY(launch_flip(w, k));
+    }
+    const Work w0{b->d_descs, b->d_map, prefix[0], b->ty, b->stream};
+    HIP_TRY(launch_measure_each(w0, b->d_n));
+    HIP_TRY(launch_bump(b->d_descs, b->n, b->d_n, 0, b->stream));
+    return SW_OK;
+}
+
+int batch_check(const sw_batch* b, uint32_t replica)
+{
+    if (!b) return fail(SW_EINVAL, "batch is NULL");
+    if (replica >= b->n) return fail(SW_EINVAL, "replica %u out of range (%u replicas)", replica, b->n);
+    return SW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_batch_workspace_bytes(const sw_params* params, uint32_t n, size_t* bytes)
+{
+    if (!bytes) return fail(SW_EINVAL, "bytes is NULL");
+    BatchLayout b;
+    int rc = batch_layout(params, n, &b);
+    if (rc) return rc;
+    *bytes = b.total;
+    return SW_OK;
+}
+
+int sw_batch_init(const sw_params* params, uint32_t n, void* dev_ws, size_t ws_bytes, void* hip_stream,
+                  sw_batch** out)
+{
+    if (!out) return fail(SW_EINVAL, "out is NULL");
+    *out = nullptr;
+    BatchLayout lay;
+    int rc = batch_layout(params, n, &lay);
+    if (rc) return rc;
+    if (!dev_ws || ((uintptr_t)dev_ws % ALIGN) != 0)
+        return fail(SW_ESPACE, "workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < lay.total) return fail(SW_ESPACE, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
+    sw_batch* b = new (std::nothrow) sw_batch();
+    if (!b) return fail(SW_EINVAL, "out of host memory");
+    b->n = n;
+    b->ty = lay.ty;
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->base = static_cast<char*>(dev_ws);
+    b->p.assign(params, params + n);
+    b->g = lay.g;
+    b->c = lay.c;
+    b->off = lay.off;
+    b->total_tiles = lay.total_tiles;
+    b->done.assign(n, 0);
+    b->first_obs.assign(n, 0);
+    b->d_descs = reinterpret_cast<LatDesc*>(b->base + lay.descs);
+    b->d_map = reinterpret_cast<WorkItem*>(b->base + lay.map);
+    b->d_n = reinterpret_cast<uint32_t*>(b->base + lay.nvec);
+    b->desc.resize(n);
+    for (uint32_t r = 0; r < n; ++r) {
+        b->desc[r] = make_desc(b->g[r], &params[r], b->base + b->off[r], b->c[r]);
+        if (!division_ok(b->g[r].L, b->desc[r].magic, b->desc[r].shift)) {
+            delete b;
+            return fail(SW_EINVAL, "internal: division by L self-check failed");
+        }
+    }
+    auto run = [&]() -> int {
+        HIP_TRY(hipMemcpyAsync(b->d_descs, b->desc.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice, b->stream));
+        for (uint32_t r = 0; r < n; ++r) {
+            char* base = b->base + b->off[r];
+            HIP_TRY(hipMemsetAsync(base + b->c[r].state, 0, sizeof(DevState), b->stream));
+            if (b->g[r].cap)
+                HIP_TRY(hipMemsetAsync(base + b->c[r].ring, 0,
+                                       (size_t)ring_slots(b->g[r]) * NCOPY * (b->g[r].q + 1) * 8, b->stream));
+            if (params[r].init) HIP_TRY(launch_init(b->d_descs, r, b->g[r].N, 1u, b->stream));
+            else HIP_TRY(hipMemsetAsync(b->desc[r].s, 0, b->g[r].N, b->stream));
+        }
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        return SW_OK;
+    };
+    rc = run();
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return SW_OK;
+}
+
+int sw_batch_sweep(sw_batch* b, const uint32_t* n_sweeps)
+{
+    if (!b || !n_sweeps) return fail(SW_EINVAL, "NULL argument");
+    for (uint32_t r = 0; r < b->n; ++r)
+        if ((uint64_t)b->done[r] + n_sweeps[r] > 0xFFFFFFFFull)
+            return fail(SW_ESTATE, "replica %u: sweep counter would overflow", r);
+    int rc = batch_enqueue(b, n_sweeps);
+    if (rc) return rc;
+    for (uint32_t r = 0; r < b->n; ++r) b->done[r] += n_sweeps[r];
+    return SW_OK;
+}
+
+int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps)
+{
+    if (!b) return fail(SW_EINVAL, "batch is NULL");
+    if (n_sweeps == 0) return SW_OK;
+    for (uint32_t r = 0; r < b->n; ++r)
+        if ((uint64_t)b->done[r] + n_sweeps > 0xFFFFFFFFull)
+            return fail(SW_ESTATE, "replica %u: sweep counter would overflow", r);
+    std::vector<uint32_t> all(b->n, n_sweeps);
+    auto it = b->graphs.find(n_sweeps);
+    // the graph bakes in the work map of "every replica"; make sure it is the one uploaded
+    std::vector<uint32_t> order(b->n);
+    for (uint32_t r = 0; r < b->n; ++r) order[r] = r;
+    if (it == b->graphs.end() || b->map_order != order) {
+        std::vector<uint32_t> prefix;
+        int rc = upload_map(b, all.data(), 1, &prefix);
+        if (rc) return rc;
+        b->h_n = all;
+        HIP_TRY(hipMemcpyAsync(b->d_n, b->h_n.data(), b->n * sizeof(uint32_t), hipMemcpyHostToDevice, b->stream));
+    }
+    if (it == b->graphs.end()) {
+        const uint32_t M = (uint32_t)b->total_tiles;
+        hipGraph_t graph;
+        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        int rc = SW_OK;
+        for (uint32_t k = 0; k < n_sweeps && rc == SW_OK; ++k) {
+            const Work w{b->d_descs, b->d_map, M, b->ty, b->stream};
+            if (launch_bond_label(w, k, k > 0 ? 1u : 0u) != hipSuccess || launch_merge(w) != hipSuccess ||
+                launch_flip(w, k) != hipSuccess)
+                rc = SW_EHIP;
+        }
+        if (rc == SW_OK) {
+            const Work w{b->d_descs, b->d_map, M, b->ty, b->stream};
+            if (launch_measure_each(w, b->d_n) != hipSuccess ||
+                launch_bump(b->d_descs, b->n, b->d_n, 0, b->stream) != hipSuccess)
+                rc = SW_EHIP;
+        }
+        const hipError_t ec = hipStreamEndCapture(b->stream, &graph);
+        if (rc != SW_OK || ec != hipSuccess) return fail(SW_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+        hipGraphExec_t exec;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(SW_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+        it = b->graphs.emplace(n_sweeps, exec).first;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, b->stream));
+    for (uint32_t r = 0; r < b->n; ++r) b->done[r] += n_sweeps;
+    return SW_OK;
+}
+
+int sw_batch_measure(sw_batch* b, uint32_t replica, uint32_t first, uint32_t n, int64_t* host_out)
+{
+    int rc = batch_check(b, replica);
+    if (rc) return rc;
+    if (!host_out && n) return fail(SW_EINVAL, "host_out is NULL");
+    const Geometry& g = b->g[replica];
+    if (g.cap == 0) return fail(SW_ESTATE, "replica %u was created with obs_capacity = 0", replica);
+    const uint64_t end = (uint64_t)first + n;
+    const uint32_t done = b->done[replica];
+    const uint64_t lo = std::max<uint64_t>(b->first_obs[replica], done > g.cap ? done - g.cap : 0);
+    if (first < lo || end > done) return fail(SW_ESTATE, "sweeps [%u, %llu) not available", first, (unsigned long long)end);
+    rc = check_device_error(b->desc[replica], b->stream);
+    if (rc) return rc;
+    return read_ring(b->desc[replica], g.N, b->stream, first, n, host_out);
+}
+
+int sw_batch_read_spins(sw_batch* b, uint32_t replica, uint8_t* host_out)
+{
+    int rc = batch_check(b, replica);
+    if (rc) return rc;
+    if (!host_out) return fail(SW_EINVAL, "host_out is NULL");
+    HIP_TRY(hipMemcpyAsync(host_out, b->desc[replica].s, b->g[replica].N, hipMemcpyDeviceToHost, b->stream));
+    return check_device_error(b->desc[replica], b->stream);
+}
+
+int sw_batch_sweeps_done(const sw_batch* b, uint32_t replica, uint32_t* out)
+{
+    int rc = batch_check(b, replica);
+    if (rc) return rc;
+    if (!out) return fail(SW_EINVAL, "out is NULL");
+    *out = b->done[replica];
+    return SW_OK;
+}
+
+int sw_batch_destroy(sw_batch* b)
+{
+    if (!b) return SW_OK;
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    delete b;
+    return SW_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,115 @@
+// Device-side building blocks of the SW sweep for gfx950 (wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sw_layout.hpp"
+
+namespace swmi {
+
+// ----------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32->64 products with the published multipliers, the key advanced by the
+// two published Weyl increments between rounds.  The key is wave-uniform, so
+// its schedule stays in scalar registers.
+struct u32x4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint32_t lo0 = 0xD2511F53u * c0;
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi1 ^ c1 ^ k0;
+        const uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return {c0, c1, c2, c3};
+}
+
+// A 32-bit draw mapped onto one of q states: floor(w q / 2^32).
+__device__ __forceinline__ uint32_t state_of_draw(uint32_t w, uint32_t q) { return __umulhi(w, q); }
+
+// New state of the cluster whose root (smallest site index) is r in sweep t.
+__device__ __forceinline__ uint32_t cluster_state(const LatDesc& d, uint32_t r, uint32_t t)
+{
+    return state_of_draw(philox4x32_10(r, 0u, t, 1u, d.key0, d.key1).x, d.q);
+}
+
+// -------------------------------------------------------------- division
+// n / L for any 32-bit n by multiply-high (Granlund & Montgomery, PLDI'94,
+// unsigned division by an invariant with a 33-bit multiplier).
+__device__ __forceinline__ uint32_t div_L(const LatDesc& d, uint32_t n)
+{
+    const uint32_t t = __umulhi(d.magic, n);
+    return (t + ((n - t) >> 1)) >> d.shift;
+}
+
+// ----------------------------------------------------------- wave helpers
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+
+__device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
+
+// Spread the 32 low bits of v to the even bit positions of a 64-bit word.
+__device__ __forceinline__ uint64_t spread_even(uint32_t v)
+{
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+// Lane l of a wave holds sites 2l (even) and 2l+1 (odd) of a 128-site row
+// segment; turn the two 64-bit ballots into the segment's two words.
+__device__ __forceinline__ void interleave_row(uint64_t even, uint64_t odd, uint64_t& w0, uint64_t& w1)
+{
+    w0 = spread_even((uint32_t)even) | (spread_even((uint32_t)odd) << 1);
+    w1 = spread_even((uint32_t)(even >> 32)) | (spread_even((uint32_t)(odd >> 32)) << 1);
+}
+
+// mask of bits 0..b (b in 0..63)
+__device__ __forceinline__ uint64_t upto(uint32_t b) { return (2ull << b) - 1ull; }
+
+__device__ __forceinline__ uint32_t msb64(uint64_t v) { return 63u - (uint32_t)__clzll(v); }
+
+// ------------------------------------------------------- coherent access
+// Labels are shared between workgroups on different XCDs while the merge runs,
+// so every access there goes through device-coherent atomics.
+__device__ __forceinline__ uint32_t ld_coherent(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coherent(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t min_coherent(uint32_t* p, uint32_t v)
+{
+    return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tile index of workgroup b when n tiles are spread over the 8 XCDs: workgroups
+// are dealt to XCDs round-robin, so XCD x gets a contiguous band of tiles and
+// horizontally adjacent tiles run back to back on the same L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t n)
+{
+    const uint32_t q8 = n >> 3, r8 = n & 7u;
+    const uint32_t x = b & 7u, k = b >> 3;
+    return (x < r8) ? x * (q8 + 1u) + k : r8 * (q8 + 1u) + (x - r8) * q8 + k;
+}
+
+}  // namespace swmi

@@ -1,0 +1,32 @@
+// Host-side launchers of the SW kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "sw_layout.hpp"
+
+namespace swmi {
+
+// What one sweep phase runs over: the tiles of descs[0] when map is null
+// (nitems = its tile count), else the work items of map (batched form).
+struct Work {
+    const LatDesc* descs;
+    const WorkItem* map;
+    uint32_t nitems;
+    uint32_t ty;
+    hipStream_t stream;
+};
+
+hipError_t launch_bond_label(const Work& w, uint32_t k, uint32_t flags);
+hipError_t launch_merge(const Work& w);
+hipError_t launch_flip(const Work& w, uint32_t k);
+hipError_t launch_measure(const Work& w, uint32_t k);
+// measurement after n_each[lattice] sweeps of each lattice (batched form)
+hipError_t launch_measure_each(const Work& w, const uint32_t* n_each);
+hipError_t launch_init(const LatDesc* descs, uint32_t lat, size_t N, uint32_t random_start, hipStream_t s);
+hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, size_t N, hipStream_t s);
+hipError_t launch_bump(const LatDesc* descs, uint32_t count, const uint32_t* n_each, uint32_t n, hipStream_t s);
+
+}  // namespace swmi

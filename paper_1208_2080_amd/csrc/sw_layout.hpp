@@ -1,0 +1,64 @@
+// Data layout of one lattice in device memory, shared by kernels and host runtime.
+//
+// Per lattice (all arrays row-major, site i = y*L + x):
+//   spins   uint8  [N]
+//   labels  uint32 [N]        after a sweep: non-root sites hold the smallest
+//                             site index of their tile-local cluster; tile-local
+//                             roots hold their parent in the global forest
+//   bonds   uint64 [2][L][W]  W = ceil(L/64); +x plane then +y plane
+//   edges   uint32 [tiles][EDGE_WORDS(TY)]  per-tile boundary record (below)
+//   ring    int64  [cap][NCOPY][q+1]  per-sweep sums: n_unsat, n_active,
+//                             n_1..n_{q-1} (n_0 = N - the rest), NCOPY partial
+//                             copies to spread atomic traffic
+//   counter uint32            sweeps done
+#pragma once
+
+#include <stdint.h>
+
+namespace swmi {
+
+constexpr uint32_t TX = 128;          // tile width: one wave, two sites per lane
+constexpr uint32_t NCOPY = 16;        // partial copies of each ring record
+constexpr uint32_t TERM = 0x80000000u;
+constexpr uint32_t CAP_STEPS = 1u << 26;  // safety cap on any pointer-chasing loop
+constexpr uint32_t INVALID = 0xFFFFFFFFu;
+
+// Boundary record of a tile with TY rows (uint32 words):
+//   [0, 4)            right-edge crossing bonds, bit r = +x bond of (w-1, r)
+//   [4, 8)            bottom-edge crossing bonds, bit x = +y bond of (x, h-1)
+//   [8, 8+TY)         labels of the right column
+//   [8+TY, 8+2TY)     labels of the left column
+//   [8+2TY, +TX)      labels of the bottom row
+//   [8+2TY+TX, +TX)   labels of the top row
+__host__ __device__ constexpr uint32_t edge_words(uint32_t ty) { return 8u + 2u * ty + 2u * TX; }
+
+struct DevState {
+    uint32_t err;          // nonzero: a safety cap tripped
+    uint32_t counter;      // sweeps done (plain lattice)
+    uint32_t pad[62];
+};
+
+struct LatDesc {
+    uint8_t* s;
+    uint32_t* lab;
+    uint64_t* bonds;
+    uint32_t* edges;
+    int64_t* ring;
+    uint32_t* counter;     // sweeps done
+    uint32_t* err;         // -> DevState::err
+    uint32_t L, q, W;
+    uint32_t ntx, nty, ntiles;
+    uint32_t cap;          // ring capacity in sweeps (0 = no measurement)
+    uint32_t thr_m1;       // threshold - 1 (bond active iff draw <= thr_m1 and thr_nz)
+    uint32_t thr_nz;       // threshold != 0
+    uint32_t key0, key1;
+    uint32_t magic, shift; // division by L
+    uint32_t pad0;
+};
+
+// Block-to-work map entry of the batched form: lattice index and tile index.
+struct WorkItem {
+    uint32_t lat, tile;
+};
+
+}  // namespace swmi

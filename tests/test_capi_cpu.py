@@ -1,0 +1,87 @@
+"""The C-ABI library builds, loads without a GPU and exports every function that
+include/sw.h declares; host-side logic (parameter checks, workspace sizes, the
+bond threshold) behaves as documented.  No kernel runs here."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import oracle
+from paper_1208_2080_amd import binding
+from paper_1208_2080_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "sw.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sw_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.lib()
+    names = _declared_functions()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding marshals exactly the declared set
+    assert sorted(n for n, _, _ in binding.SIGNATURES) == names
+
+
+def test_threshold_matches_oracle():
+    for K in [0.0, 0.1, 0.5, wl.critical_coupling(2), wl.critical_coupling(3), 2.0, 7.5, 40.0, float("inf")]:
+        assert binding.threshold(K) == oracle.threshold(K)
+    with pytest.raises(binding.SwError) as e:
+        binding.threshold(-1.0)
+    assert e.value.code == binding.SW_EINVAL
+    with pytest.raises(binding.SwError):
+        binding.threshold(float("nan"))
+
+
+def _ws(L, q=2, cap=2, ty=0):
+    p = binding.make_params(L, q, 1.0, obs_capacity=cap, tile_rows=ty)
+    return binding.lib().sw_workspace_bytes(ctypes.byref(p))
+
+
+def test_workspace_sizes():
+    # spins + labels + bond planes + edge records + ring, each 256-byte aligned
+    for L in [2, 64, 100, 4096, 16384]:
+        n = _ws(L)
+        assert n >= 5 * L * L + 2 * L * math.ceil(L / 64) * 8
+        assert n % 256 == 0
+    big = _ws(65536, 2, 1024)
+    assert 21.0 * 2**30 < big < 23.5 * 2**30      # ~5.25 B/site + tile edge records
+    assert _ws(1000, 2, 1000) > _ws(1000, 2, 2)
+
+
+@pytest.mark.parametrize("L,q,K,cap,ty", [(1, 2, 1.0, 2, 0), (65537, 2, 1.0, 2, 0), (8, 1, 1.0, 2, 0),
+                                          (8, 256, 1.0, 2, 0), (8, 2, -0.5, 2, 0), (8, 2, float("nan"), 2, 0),
+                                          (8, 2, 1.0, 1, 0), (8, 2, 1.0, 2, 48)])
+def test_invalid_params_rejected(L, q, K, cap, ty):
+    p = binding.make_params(L, q, K, obs_capacity=cap, tile_rows=ty)
+    assert binding.lib().sw_workspace_bytes(ctypes.byref(p)) == 0
+    assert binding.lib().sw_last_error().decode() != ""
+
+
+def test_init_rejects_bad_workspace_without_touching_the_gpu():
+    lib = binding.lib()
+    p = binding.make_params(16, 2, 1.0)
+    h = ctypes.c_void_p()
+    need = lib.sw_workspace_bytes(ctypes.byref(p))
+    # NULL / misaligned / too small workspaces are refused before any HIP call
+    assert lib.sw_init(ctypes.byref(p), None, need, None, ctypes.byref(h)) == binding.SW_ESPACE
+    assert lib.sw_init(ctypes.byref(p), ctypes.c_void_p(0x1001), need, None, ctypes.byref(h)) == binding.SW_ESPACE
+    assert lib.sw_init(ctypes.byref(p), ctypes.c_void_p(0x10000), need - 256, None,
+                       ctypes.byref(h)) == binding.SW_ESPACE
+    assert not h.value
+    bad = binding.make_params(16, 2, -1.0)
+    assert lib.sw_init(ctypes.byref(bad), ctypes.c_void_p(0x10000), need, None, ctypes.byref(h)) == binding.SW_EINVAL
+    n = ctypes.c_size_t()
+    arr = (binding.SwParams * 2)(binding.make_params(16, 2, 1.0, tile_rows=32), binding.make_params(16, 2, 1.0))
+    assert lib.sw_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == binding.SW_EINVAL   # mixed tile heights
+    arr = (binding.SwParams * 2)(binding.make_params(16, 2, 1.0), binding.make_params(40, 3, 0.5))
+    assert lib.sw_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == binding.SW_OK
+    assert n.value >= _ws(16) + _ws(40, 3)

@@ -1,0 +1,159 @@
+"""GPU parity: the HIP sweep against the CPU oracle, element by element.
+
+Spins, cluster labels, bond planes and the int64 observables must be bit
+identical after every sweep; the FP64 quantities derived on the host from the
+int64 observables must agree within 1e-12 relative (they come from identical
+integers through one formula, so they are in fact equal).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1208_2080_amd import binding
+from paper_1208_2080_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def compare_sweeps(L, q, K, seed, random_start=True, sweeps=10, tile_rows=0, labels_every=1,
+                   spins=None, start=0):
+    say(f"case L={L} q={q} K={K} seed={seed} random={random_start} sweeps={sweeps} ty={tile_rows}")
+    lat = binding.Lattice(L, q, K, seed=seed, random_start=random_start, obs_capacity=max(2, sweeps),
+                          tile_rows=tile_rows)
+    ref = oracle.OracleLattice(L, q, K, seed, random_start=random_start, spins=spins, sweep=start)
+    if spins is not None:
+        lat.load_spins(spins, start)
+    assert np.array_equal(lat.spins(), ref.s), "initial spins"
+    for k in range(sweeps):
+        t = start + k
+        lat.sweep(1)
+        out = ref.sweep()
+        got = lat.spins()
+        if not np.array_equal(got, ref.s):
+            bad = np.argwhere(got != ref.s)
+            raise AssertionError(f"spins differ after sweep {t} at {len(bad)} sites, first {bad[:5].tolist()}")
+        if labels_every and k % labels_every == 0:
+            bx, by = lat.bonds()
+            assert np.array_equal(bx, oracle.pack_bonds(out["bx"])), f"+x bonds differ in sweep {t}"
+            assert np.array_equal(by, oracle.pack_bonds(out["by"])), f"+y bonds differ in sweep {t}"
+            assert np.array_equal(lat.labels(), out["labels"]), f"labels differ in sweep {t}"
+        obs = lat.measure(t, 1)[0]
+        assert np.array_equal(obs, out["obs"]), f"observables differ after sweep {t}: {obs} vs {out['obs']}"
+        d_gpu = binding.derived(obs, L, q)
+        d_ref = binding.derived(out["obs"], L, q)
+        for key in d_ref:
+            assert math.isclose(d_gpu[key], d_ref[key], rel_tol=1e-12, abs_tol=0.0) or d_gpu[key] == d_ref[key]
+    lat.close()
+    return ref
+
+
+def test_small_config_every_sweep():
+    """64 x 64, q = 2 at K_c, random start, 1000 sweeps: spins and int64
+    observables after every sweep, labels and bonds every 25th sweep."""
+    c = wl.SMALL
+    compare_sweeps(c["L"], c["q"], c["K"], c["seed"], True, sweeps=c["sweeps"], labels_every=25)
+
+
+@pytest.mark.parametrize("seed", [2, 3, 4])
+def test_small_config_other_seeds(seed):
+    c = wl.SMALL
+    compare_sweeps(c["L"], c["q"], c["K"], seed, True, sweeps=60, labels_every=5)
+
+
+@pytest.mark.parametrize("L", [2, 3, 5, 17, 63, 65, 127, 128, 129, 130, 200, 255, 257, 300])
+def test_ragged_sizes(L):
+    compare_sweeps(L, 2, wl.critical_coupling(2), seed=L, sweeps=8)
+
+
+@pytest.mark.parametrize("q", [3, 4, 7, 10, 17, 255])
+def test_many_states(q):
+    compare_sweeps(96, q, wl.critical_coupling(q), seed=10 + q, sweeps=8)
+    compare_sweeps(33, q, wl.critical_coupling(q), seed=20 + q, sweeps=5, random_start=False)
+
+
+@pytest.mark.parametrize("ty", [32, 64, 128])
+@pytest.mark.parametrize("L", [100, 256, 383])
+def test_tile_heights(ty, L):
+    compare_sweeps(L, 3, wl.critical_coupling(3), seed=5, sweeps=6, tile_rows=ty)
+
+
+def test_zero_coupling_singletons():
+    compare_sweeps(70, 5, 0.0, seed=3, sweeps=4)
+
+
+def test_infinite_coupling_cold_start_one_cluster():
+    ref = compare_sweeps(150, 3, float("inf"), seed=9, random_start=False, sweeps=3)
+    assert len(np.unique(ref.s)) == 1
+
+
+def test_strong_coupling_wrapping_clusters():
+    compare_sweeps(260, 2, 3.0, seed=11, sweeps=6)
+
+
+def test_checkerboard_has_no_bonds():
+    compare_sweeps(128, 2, float("inf"), seed=4, sweeps=1, spins=wl.checkerboard(128))
+
+
+def test_resume_from_checkpoint():
+    L, q, K = 200, 3, wl.critical_coupling(3)
+    a = binding.Lattice(L, q, K, seed=77, obs_capacity=64)
+    a.sweep(20)
+    straight = a.spins()
+    obs_straight = a.measure(10, 10)
+    b = binding.Lattice(L, q, K, seed=77, obs_capacity=64)
+    b.sweep(10)
+    snap = b.spins()
+    c = binding.Lattice(L, q, K, seed=77, obs_capacity=64)
+    c.load_spins(snap, 10)
+    c.sweep(10)
+    assert np.array_equal(c.spins(), straight)
+    assert np.array_equal(c.measure(10, 10), obs_straight)
+    with pytest.raises(binding.SwError):
+        c.measure(9, 1)                       # before the checkpoint: not available
+
+
+def test_multi_sweep_calls_match_single_sweeps():
+    L, q, K = 256, 2, wl.critical_coupling(2)
+    ref = oracle.OracleLattice(L, q, K, 5)
+    ref_obs = ref.run(37)
+    lat = binding.Lattice(L, q, K, seed=5, obs_capacity=64)
+    for n in (1, 5, 13, 18):
+        lat.sweep(n)
+    assert lat.sweeps_done == 37
+    assert np.array_equal(lat.spins(), ref.s)
+    assert np.array_equal(lat.measure(0, 37), ref_obs)
+
+
+def test_ring_wraps():
+    L, q, K = 64, 2, wl.critical_coupling(2)
+    ref = oracle.OracleLattice(L, q, K, 8)
+    ref_obs = ref.run(30)
+    lat = binding.Lattice(L, q, K, seed=8, obs_capacity=4)
+    lat.sweep(30)
+    assert np.array_equal(lat.measure(26, 4), ref_obs[26:])
+    with pytest.raises(binding.SwError):
+        lat.measure(25, 1)
+
+
+def test_errors_surface_as_codes():
+    lat = binding.Lattice(16, 3, 1.0, seed=1, obs_capacity=4)
+    with pytest.raises(binding.SwError) as e:
+        lat.load_spins(np.full((16, 16), 3, np.uint8), 0)
+    assert e.value.code == binding.SW_EINVAL
+    with pytest.raises(binding.SwError) as e:
+        lat.labels()
+    assert e.value.code == binding.SW_ESTATE
+    lat.sweep(2)
+    with pytest.raises(binding.SwError) as e:
+        lat.measure(0, 3)
+    assert e.value.code == binding.SW_ESTATE
