@@ -66,6 +66,7 @@ typedef struct sw_params {
 
 typedef struct sw_lattice sw_lattice;
 typedef struct sw_batch sw_batch;
+typedef struct sw_group sw_group;
 
 /* Device bytes one lattice needs; 0 if the parameters are invalid. */
 size_t sw_workspace_bytes(const sw_params* p);
@@ -144,6 +145,26 @@ int sw_batch_measure(sw_batch* b, uint32_t replica, uint32_t first, uint32_t n, 
 int sw_batch_read_spins(sw_batch* b, uint32_t replica, uint8_t* host_out);
 int sw_batch_sweeps_done(const sw_batch* b, uint32_t replica, uint32_t* out);
 int sw_batch_destroy(sw_batch* b);
+
+/* ----------------------------------------------------------------- groups
+ * Continuous batching: one launch per phase over any set of lattices made by
+ * sw_init (same tile_rows, same stream), which may change from call to call.
+ * Each lattice is swept exactly as sw_sweep would (same random draws). */
+
+/* Tiles of one lattice (the unit of work of every launch). */
+int sw_tile_count(const sw_params* p, uint32_t* tiles);
+
+/* Device bytes of a group's scratch for up to max_lattices lattices holding up
+ * to max_tiles tiles in total. */
+int sw_group_workspace_bytes(uint32_t max_lattices, uint64_t max_tiles, size_t* bytes);
+
+int sw_group_init(uint32_t max_lattices, uint64_t max_tiles, uint32_t tile_rows, void* dev_ws, size_t ws_bytes,
+                  void* hip_stream, sw_group** out);
+
+/* Sweep lats[i] n_sweeps[i] times (0 = leave it alone); asynchronous. */
+int sw_group_sweep(sw_group* g, sw_lattice* const* lats, const uint32_t* n_sweeps, uint32_t n);
+
+int sw_group_destroy(sw_group* g);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* sw_last_error(void);

@@ -4,7 +4,7 @@ AMD Instinct MI355X, as hand-written HIP kernels behind a C ABI (include/sw.h).
 ``Lattice`` / ``Batch`` and friends live in ``binding`` and are imported lazily
 (they need torch); ``workloads`` holds the seeded synthetic inputs.
 """
-__all__ = ["Lattice", "Batch", "SwError", "threshold", "workspace_bytes", "derived", "lib"]
+__all__ = ["Lattice", "Batch", "Group", "SwError", "threshold", "workspace_bytes", "tile_count", "derived", "lib"]
 
 
 def __getattr__(name):

@@ -56,6 +56,11 @@ SIGNATURES = [
     ("sw_batch_read_spins", ctypes.c_int, [_VP, _U32, _VP]),
     ("sw_batch_sweeps_done", ctypes.c_int, [_VP, _U32, ctypes.POINTER(_U32)]),
     ("sw_batch_destroy", ctypes.c_int, [_VP]),
+    ("sw_tile_count", ctypes.c_int, [_PP, ctypes.POINTER(_U32)]),
+    ("sw_group_workspace_bytes", ctypes.c_int, [_U32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_size_t)]),
+    ("sw_group_init", ctypes.c_int, [_U32, ctypes.c_uint64, _U32, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    ("sw_group_sweep", ctypes.c_int, [_VP, _VP, _VP, _U32]),
+    ("sw_group_destroy", ctypes.c_int, [_VP]),
     ("sw_last_error", ctypes.c_char_p, []),
 ]
 
@@ -264,3 +269,44 @@ class Batch:
         except Exception:
             pass
 
+
+
+def tile_count(L: int, q: int = 2, tile_rows: int = 0) -> int:
+    v = ctypes.c_uint32()
+    _check(lib().sw_tile_count(ctypes.byref(make_params(L, q, 1.0, tile_rows=tile_rows)), ctypes.byref(v)))
+    return int(v.value)
+
+
+class Group:
+    """One launch per phase over any set of ``Lattice`` objects (continuous batching)."""
+
+    def __init__(self, max_lattices: int, max_tiles: int, tile_rows: int = 0, device=None, stream=None):
+        self.max_lattices, self.max_tiles = int(max_lattices), int(max_tiles)
+        nbytes = ctypes.c_size_t()
+        _check(lib().sw_group_workspace_bytes(self.max_lattices, self.max_tiles, ctypes.byref(nbytes)))
+        self.device = torch.device("cuda", 0) if device is None else torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self._h = ctypes.c_void_p()
+        _check(lib().sw_group_init(self.max_lattices, self.max_tiles, int(tile_rows),
+                                   ctypes.c_void_p(self.ws.data_ptr()), nbytes.value,
+                                   ctypes.c_void_p(_stream_handle(self.stream)), ctypes.byref(self._h)))
+
+    def sweep(self, lattices, n_each):
+        n = len(lattices)
+        handles = (ctypes.c_void_p * max(1, n))(*[lat._h.value for lat in lattices])
+        counts = np.ascontiguousarray(n_each, dtype=np.uint32)
+        assert counts.size == n
+        _check(lib().sw_group_sweep(self._h, handles, counts.ctypes.data_as(ctypes.c_void_p), n))
+
+    def close(self):
+        if self._h:
+            lib().sw_group_destroy(self._h)
+            self._h = ctypes.c_void_p()
+        self.ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

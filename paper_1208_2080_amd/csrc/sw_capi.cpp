@@ -106,7 +106,7 @@ Carve carve(const Geometry& g)
     c.desc = take(sizeof(LatDesc));
     c.spins = take(g.N);
     c.lab = take(g.N * 4);
-    c.bonds = take((size_t)2 * g.L * g.W * 8);
+    c.bonds = take((size_t)g.ntiles * 2 * g.ty * 8);
     c.edges = take((size_t)g.ntiles * edge_words(g.ty) * 4);
     c.ring = take((size_t)ring_slots(g) * NCOPY * (g.q + 1) * 8);
     c.total = off;
@@ -156,6 +156,9 @@ LatDesc make_desc(const Geometry& g, const sw_params* p, char* base, const Carve
     d.key0 = (uint32_t)p->seed;
     d.key1 = (uint32_t)(p->seed >> 32);
     division_magic(g.L, &d.magic, &d.shift);
+    d.log2L = 0;
+    if ((g.L & (g.L - 1)) == 0)
+        while ((1u << d.log2L) < g.L) ++d.log2L;
     return d;
 }
 
@@ -187,23 +190,28 @@ int check_device_error(const LatDesc& d, hipStream_t s)
 }
 
 // Sum the NCOPY partial copies of ring records [first, first+n) into rows of
-// (2 + q) int64: n_unsat, n_active, n_0..n_{q-1}.
+// (2 + q) int64: n_unsat, n_active, n_0..n_{q-1}.  The records are copied in at
+// most two contiguous pieces (the ring may wrap) and one synchronisation.
 int read_ring(const LatDesc& d, size_t N, hipStream_t s, uint32_t first, uint32_t n, int64_t* out)
 {
-    const uint32_t R = d.q + 1;
-    std::vector<int64_t> buf((size_t)NCOPY * R);
+    if (n == 0) return SW_OK;
+    const size_t R = d.q + 1, rec = (size_t)NCOPY * R;
+    std::vector<int64_t> buf((size_t)n * rec);
+    const uint32_t slot0 = first % d.cap;
+    const uint32_t n1 = std::min<uint32_t>(n, d.cap - slot0);
+    HIP_TRY(hipMemcpyAsync(buf.data(), d.ring + (size_t)slot0 * rec, (size_t)n1 * rec * 8, hipMemcpyDeviceToHost, s));
+    if (n1 < n)
+        HIP_TRY(hipMemcpyAsync(buf.data() + (size_t)n1 * rec, d.ring, (size_t)(n - n1) * rec * 8,
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
     for (uint32_t k = 0; k < n; ++k) {
-        const uint32_t t = first + k;
-        const int64_t* src = d.ring + (size_t)(t % d.cap) * NCOPY * R;
-        HIP_TRY(hipMemcpyAsync(buf.data(), src, buf.size() * 8, hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
         int64_t* row = out + (size_t)k * (2 + d.q);
         std::memset(row, 0, (2 + d.q) * 8);
         for (uint32_t cpy = 0; cpy < NCOPY; ++cpy) {
-            const int64_t* rec = buf.data() + (size_t)cpy * R;
-            row[0] += rec[0];
-            row[1] += rec[1];
-            for (uint32_t c = 1; c < d.q; ++c) row[2 + c] += rec[1 + c];
+            const int64_t* r = buf.data() + (size_t)k * rec + (size_t)cpy * R;
+            row[0] += r[0];
+            row[1] += r[1];
+            for (uint32_t c = 1; c < d.q; ++c) row[2 + c] += r[1 + c];
         }
         int64_t rest = 0;
         for (uint32_t c = 1; c < d.q; ++c) rest += row[2 + c];
@@ -408,9 +416,20 @@ int sw_read_bonds(sw_lattice* h, uint64_t* host_out)
 {
     if (!h || !host_out) return fail(SW_EINVAL, "NULL argument");
     if (!h->have_sweep) return fail(SW_ESTATE, "no sweep since init / load");
-    HIP_TRY(hipMemcpyAsync(host_out, h->desc.bonds, (size_t)2 * h->g.L * h->g.W * 8, hipMemcpyDeviceToHost,
-                           h->stream));
-    return check_device_error(h->desc, h->stream);
+    const Geometry& g = h->g;
+    std::vector<uint64_t> tiles((size_t)g.ntiles * 2 * g.ty);
+    HIP_TRY(hipMemcpyAsync(tiles.data(), h->desc.bonds, tiles.size() * 8, hipMemcpyDeviceToHost, h->stream));
+    const int rc = check_device_error(h->desc, h->stream);
+    if (rc) return rc;
+    // tile-major words -> two row-major planes of L rows by W words (W = tiles per row)
+    for (uint32_t t = 0; t < g.ntiles; ++t) {
+        const uint32_t ty = t / g.ntx, tx = t % g.ntx;
+        const uint32_t y0 = ty * g.ty, rows = std::min(g.ty, g.L - y0);
+        for (uint32_t p = 0; p < 2; ++p)
+            for (uint32_t r = 0; r < rows; ++r)
+                host_out[((size_t)p * g.L + y0 + r) * g.W + tx] = tiles[((size_t)t * 2 + p) * g.ty + r];
+    }
+    return SW_OK;
 }
 
 int sw_destroy(sw_lattice* h)
@@ -728,6 +747,162 @@ int sw_batch_destroy(sw_batch* b)
     if (!b) return SW_OK;
     for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
     delete b;
+    return SW_OK;
+}
+
+}  // extern "C"
+
+// -------------------------------------------------------------------- groups
+// A group sweeps any set of separately initialised lattices (same tile height,
+// same stream) with one launch per phase: the continuous-batching primitive,
+// where lattices join and leave between calls.  Its device scratch (descriptor
+// table, work map, per-lattice sweep counts) comes from the caller's workspace.
+struct sw_group {
+    uint32_t max_lat;
+    uint64_t max_tiles;
+    uint32_t ty;
+    hipStream_t stream;
+    LatDesc* d_descs;
+    WorkItem* d_map;
+    uint32_t* d_n;
+    std::vector<LatDesc> h_desc;
+    std::vector<WorkItem> h_map;
+    std::vector<uint32_t> h_n;
+};
+
+namespace {
+
+struct GroupLayout {
+    size_t descs, map, nvec, total;
+};
+
+GroupLayout group_layout(uint32_t max_lat, uint64_t max_tiles)
+{
+    GroupLayout g{};
+    size_t off = 0;
+    g.descs = off;
+    off = align_up(off + sizeof(LatDesc) * max_lat);
+    g.map = off;
+    off = align_up(off + sizeof(WorkItem) * max_tiles);
+    g.nvec = off;
+    off = align_up(off + sizeof(uint32_t) * max_lat);
+    g.total = off;
+    return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sw_tile_count(const sw_params* p, uint32_t* tiles)
+{
+    if (!tiles) return fail(SW_EINVAL, "tiles is NULL");
+    Geometry g;
+    const int rc = check_params(p, &g);
+    if (rc) return rc;
+    *tiles = g.ntiles;
+    return SW_OK;
+}
+
+int sw_group_workspace_bytes(uint32_t max_lattices, uint64_t max_tiles, size_t* bytes)
+{
+    if (!bytes) return fail(SW_EINVAL, "bytes is NULL");
+    if (max_lattices == 0 || max_tiles == 0 || max_tiles >= 0xFFFFFFFFull)
+        return fail(SW_EINVAL, "need 1 <= max_lattices and 1 <= max_tiles < 2^32");
+    *bytes = group_layout(max_lattices, max_tiles).total;
+    return SW_OK;
+}
+
+int sw_group_init(uint32_t max_lattices, uint64_t max_tiles, uint32_t tile_rows, void* dev_ws, size_t ws_bytes,
+                  void* hip_stream, sw_group** out)
+{
+    if (!out) return fail(SW_EINVAL, "out is NULL");
+    *out = nullptr;
+    size_t need = 0;
+    int rc = sw_group_workspace_bytes(max_lattices, max_tiles, &need);
+    if (rc) return rc;
+    const uint32_t ty = tile_rows ? tile_rows : DEFAULT_TY;
+    if (ty != 32 && ty != 64 && ty != 128) return fail(SW_EINVAL, "tile_rows must be 0, 32, 64 or 128");
+    if (!dev_ws || ((uintptr_t)dev_ws % ALIGN) != 0)
+        return fail(SW_ESPACE, "workspace must be a 256-byte aligned device pointer");
+    if (ws_bytes < need) return fail(SW_ESPACE, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    sw_group* g = new (std::nothrow) sw_group();
+    if (!g) return fail(SW_EINVAL, "out of host memory");
+    const GroupLayout lay = group_layout(max_lattices, max_tiles);
+    char* base = static_cast<char*>(dev_ws);
+    g->max_lat = max_lattices;
+    g->max_tiles = max_tiles;
+    g->ty = ty;
+    g->stream = static_cast<hipStream_t>(hip_stream);
+    g->d_descs = reinterpret_cast<LatDesc*>(base + lay.descs);
+    g->d_map = reinterpret_cast<WorkItem*>(base + lay.map);
+    g->d_n = reinterpret_cast<uint32_t*>(base + lay.nvec);
+    *out = g;
+    return SW_OK;
+}
+
+int sw_group_sweep(sw_group* g, sw_lattice* const* lats, const uint32_t* n_sweeps, uint32_t n)
+{
+    if (!g || (n && (!lats || !n_sweeps))) return fail(SW_EINVAL, "NULL argument");
+    if (n > g->max_lat) return fail(SW_EINVAL, "%u lattices exceed the group's %u", n, g->max_lat);
+    uint64_t tiles = 0;
+    uint32_t kmax = 0;
+    for (uint32_t i = 0; i < n; ++i) {
+        const sw_lattice* h = lats[i];
+        if (!h) return fail(SW_EINVAL, "lattice %u is NULL", i);
+        if (h->g.ty != g->ty) return fail(SW_EINVAL, "lattice %u has tile_rows %u, group %u", i, h->g.ty, g->ty);
+        if (h->stream != g->stream) return fail(SW_EINVAL, "lattice %u is bound to another stream", i);
+        if ((uint64_t)h->done + n_sweeps[i] > 0xFFFFFFFFull)
+            return fail(SW_ESTATE, "lattice %u: sweep counter would overflow", i);
+        for (uint32_t j = 0; j < i; ++j)
+            if (lats[j] == h) return fail(SW_EINVAL, "lattice %u appears twice", i);
+        if (n_sweeps[i]) tiles += h->g.ntiles;
+        kmax = std::max(kmax, n_sweeps[i]);
+    }
+    if (tiles > g->max_tiles) return fail(SW_EINVAL, "%llu tiles exceed the group's %llu",
+                                          (unsigned long long)tiles, (unsigned long long)g->max_tiles);
+    if (kmax == 0) return SW_OK;
+    // work map: tiles of the lattices still sweeping at step k form a prefix
+    std::vector<uint32_t> order;
+    for (uint32_t i = 0; i < n; ++i)
+        if (n_sweeps[i]) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t c) { return n_sweeps[a] > n_sweeps[c]; });
+    g->h_desc.resize(n);
+    g->h_n.assign(n_sweeps, n_sweeps + n);
+    g->h_map.clear();
+    for (uint32_t i = 0; i < n; ++i) g->h_desc[i] = lats[i]->desc;
+    std::vector<uint32_t> ends;
+    for (uint32_t i : order) {
+        for (uint32_t t = 0; t < lats[i]->g.ntiles; ++t) g->h_map.push_back({i, t});
+        ends.push_back((uint32_t)g->h_map.size());
+    }
+    HIP_TRY(hipMemcpyAsync(g->d_descs, g->h_desc.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice, g->stream));
+    HIP_TRY(hipMemcpyAsync(g->d_map, g->h_map.data(), sizeof(WorkItem) * g->h_map.size(), hipMemcpyHostToDevice,
+                           g->stream));
+    HIP_TRY(hipMemcpyAsync(g->d_n, g->h_n.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, g->stream));
+    size_t pos = order.size();
+    for (uint32_t k = 0; k < kmax; ++k) {
+        while (pos > 0 && n_sweeps[order[pos - 1]] <= k) --pos;
+        const Work w{g->d_descs, g->d_map, pos ? ends[pos - 1] : 0u, g->ty, g->stream};
+        HIP_TRY(launch_bond_label(w, k, k > 0 ? 1u : 0u));
+        HIP_TRY(launch_merge(w));
+        HIP_TRY(launch_flip(w, k));
+    }
+    const Work w0{g->d_descs, g->d_map, ends.back(), g->ty, g->stream};
+    HIP_TRY(launch_measure_each(w0, g->d_n));
+    HIP_TRY(launch_bump(g->d_descs, n, g->d_n, 0, g->stream));
+    for (uint32_t i = 0; i < n; ++i)
+        if (n_sweeps[i]) {
+            lats[i]->done += n_sweeps[i];
+            lats[i]->have_sweep = true;
+        }
+    return SW_OK;
+}
+
+int sw_group_destroy(sw_group* g)
+{
+    delete g;
     return SW_OK;
 }
 

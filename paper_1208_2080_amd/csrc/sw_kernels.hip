@@ -1,8 +1,9 @@
 // HIP kernels of one Swendsen-Wang sweep for gfx950, plus their launchers.
 //
-// One sweep is three launches over the tiles of the lattice (TX = 128 columns
-// by TY rows, one 256-thread workgroup per tile):
-//   k_bond_label  bonds (Sec. 2 step (1)) + tile-local cluster labelling in LDS
+// One sweep is three launches over the tiles of the lattice (TX = 64 columns
+// by TY rows, one 256-thread workgroup of four waves per tile, one column per
+// lane):
+//   k_bond_label  bonds (Sec. 2 step (1)) + tile-local cluster labelling
 //                 + measurement of the configuration the bonds were drawn on
 //   k_merge       joins tile-local clusters across tile edges (global union-find
 //                 with atomicMin, larger root under smaller)
@@ -26,6 +27,7 @@ namespace {
 constexpr uint32_t LDS_CAP = 1u << 15;     // > sites of the largest tile
 constexpr uint32_t FIND_CAP = 1u << 20;    // safety cap of global pointer chases
 constexpr uint32_t UNITE_CAP = 1u << 12;   // safety cap of union retries
+constexpr uint32_t SPW = TX + 4;           // LDS row stride of staged spins (bytes)
 
 struct TileGeom {
     uint32_t tx, ty, x0, y0, w, h;
@@ -63,12 +65,27 @@ __device__ __forceinline__ bool pick(const LatDesc* descs, const WorkItem* map, 
 
 __device__ __forceinline__ void flag_error(uint32_t* err) { atomicOr(err, 1u); }
 
+// Lane l's bit of a wave-uniform mask, as a lane predicate.
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// Number of set bits of a wave-uniform mask below this lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Value of the neighbouring lane of the pair (lane ^ 1).
+__device__ __forceinline__ uint32_t swap_pair(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+}
+
 // ------------------------------------------------------- LDS union-find
-// P holds, for every site of the tile, a tile-local index that is never larger
-// than the site's own; roots point at themselves.  Finds halve paths with
-// plain stores (a stored value is always an ancestor, so races are benign);
-// unions hook the larger root under the smaller one with atomicMin and retry
-// from the old value when the hooked node was no longer a root.
+// P holds, for every provisional label of the tile, a label that is never
+// larger than itself; roots point at themselves.  Finds halve paths with plain
+// stores (a stored value is always an ancestor, so races are benign); unions
+// hook the larger root under the smaller one with atomicMin and retry from the
+// old value when the hooked node was no longer a root.
 __device__ __forceinline__ uint32_t lds_ld(uint32_t* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -163,34 +180,70 @@ __device__ uint32_t g_root(const uint32_t* lab, uint32_t x, uint32_t* err)
     return x;
 }
 
-// ------------------------------------------------------------ row access
-// Lane l holds sites x0+2l and x0+2l+1 of a row (a = even offset, b = odd).
-struct RowSpins {
-    uint32_t a, b, halo;
-};
-
-__device__ __forceinline__ RowSpins load_row(const uint8_t* s, size_t base, uint32_t x0, uint32_t xa,
-                                             bool va, bool vb, uint32_t xh)
+// Root search with path compression, once the merge is over: every node on
+// the walked path is pointed straight at the root (a benign race: any value
+// written is an ancestor of the node).
+__device__ uint32_t g_root_compress(uint32_t* lab, uint32_t x, uint32_t* err)
 {
-    RowSpins r;
-    r.a = va ? s[base + x0 + xa] : 0u;
-    r.b = vb ? s[base + x0 + xa + 1] : 0u;
-    r.halo = s[base + xh];
-    return r;
+    const uint32_t root = g_root(lab, x, err);
+    for (uint32_t it = 0; it < FIND_CAP && x != root; ++it) {
+        const uint32_t p = lab[x];
+        if (p <= root) break;
+        lab[x] = root;
+        x = p;
+    }
+    return root;
 }
 
-// Count, for the measurement, the sites of this row in each state c >= 1.
-__device__ __forceinline__ void count_states(uint32_t* hist, uint32_t q, uint32_t lane, bool va, bool vb,
-                                             uint32_t sa, uint32_t sb)
+// ------------------------------------------------------------ spin staging
+// Spins of a tile and its halo in LDS: rows 0..h (row h is the row below the
+// tile, periodic), columns 0..w-1 plus column w = the column right of the tile
+// (periodic).  Row stride SPW bytes.
+template <int TY>
+__device__ __forceinline__ void stage_spins(uint8_t* sp, const LatDesc& d, const TileGeom& g, uint32_t tid)
+{
+    const uint32_t L = d.L, w = g.w, h = g.h;
+    const uint32_t yb = (g.y0 + h == L) ? 0u : g.y0 + h;          // row below the tile
+    const uint32_t xh = (g.x0 + w == L) ? 0u : g.x0 + w;          // column right of the tile
+    if ((L & 3u) == 0) {
+        // rows start 4-byte aligned (w is then a multiple of 4): 16 rows per pass
+        const uint32_t c = tid & 15u, dw = w >> 2;
+#pragma unroll
+        for (uint32_t rr = 0; rr <= (uint32_t)TY; rr += 16) {
+            const uint32_t r = rr + (tid >> 4);
+            if (r <= h && c < dw) {
+                const uint32_t y = (r < h) ? g.y0 + r : yb;
+                const uint32_t v = *reinterpret_cast<const uint32_t*>(d.s + (size_t)y * L + g.x0 + 4 * c);
+                *reinterpret_cast<uint32_t*>(sp + r * SPW + 4 * c) = v;
+            }
+        }
+    } else {
+        const uint32_t c = tid & 63u;
+#pragma unroll 4
+        for (uint32_t rr = 0; rr <= (uint32_t)TY; rr += 4) {
+            const uint32_t r = rr + (tid >> 6);
+            if (r <= h && c < w) {
+                const uint32_t y = (r < h) ? g.y0 + r : yb;
+                sp[r * SPW + c] = d.s[(size_t)y * L + g.x0 + c];
+            }
+        }
+    }
+    for (uint32_t r = tid; r <= h; r += 256) {
+        const uint32_t y = (r < h) ? g.y0 + r : yb;
+        sp[r * SPW + w] = d.s[(size_t)y * L + xh];
+    }
+}
+
+// Count, for the measurement, the sites of one row in each state c >= 1.
+__device__ __forceinline__ void count_states(uint32_t* hist, uint32_t q, uint32_t lane, bool valid, uint32_t s)
 {
     if (q <= 16) {
         for (uint32_t c = 1; c < q; ++c) {
-            const uint32_t n = popc64(ballot(va && sa == c)) + popc64(ballot(vb && sb == c));
+            const uint32_t n = popc64(ballot(valid && s == c));
             if (lane == 0 && n) atomicAdd(&hist[c], n);
         }
-    } else {
-        if (va && sa) atomicAdd(&hist[sa], 1u);
-        if (vb && sb) atomicAdd(&hist[sb], 1u);
+    } else if (valid && s) {
+        atomicAdd(&hist[s], 1u);
     }
 }
 
@@ -205,19 +258,89 @@ __device__ __forceinline__ void atomic_add_i64(int64_t* p, uint64_t v)
     atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
 }
 
+// Per-wave queue of pending unions (pairs of provisional labels, 16 bits
+// each).  Row labelling never reads the union-find, so unions can wait and
+// then run with every lane busy instead of one lane of a diverged wave.
+constexpr uint32_t QCAP = 256;
+
+struct UnionQueue {
+    uint32_t* q;   // QCAP slots in LDS
+    uint32_t n;    // wave-uniform fill
+};
+
+__device__ __forceinline__ void drain(UnionQueue& uq, uint32_t* P, uint32_t lane, uint32_t* err)
+{
+    for (uint32_t j = lane; j < uq.n; j += 64) {
+        const uint32_t e = lds_ld(&uq.q[j]);
+        lds_union(P, e & 0xFFFFu, e >> 16, err);
+    }
+    uq.n = 0;
+}
+
+__device__ __forceinline__ void enqueue(UnionQueue& uq, bool pred, uint32_t a, uint32_t b, uint32_t* P,
+                                        uint32_t lane, uint32_t* err)
+{
+    const uint64_t m = ballot(pred);
+    if (!m) return;
+    const uint32_t cnt = popc64(m);
+    if (uq.n + cnt > QCAP) drain(uq, P, lane, err);
+    if (pred) lds_st(&uq.q[uq.n + lanes_below(m)], a | (b << 16));
+    uq.n += cnt;
+}
+
+// Provisional labels of one tile row, Hoshen-Kopelman style.  hx: +x bonds
+// inside the tile; V: +y bonds from the row above (0 on a strip's first row);
+// lp: this lane's label of the row above.  Every run of +x bonds takes one
+// label: the label above one of its +y bonds, or, with none, its first site
+// (a new root).  The runs are numbered by their first sites, and one LDS slot
+// per run carries the choice to all its sites.  Any further +y bond into the
+// run from a differently labelled site queues a union.
+__device__ __forceinline__ uint32_t row_labels(uint32_t* P, uint32_t* rl, UnionQueue& uq, uint32_t r, uint32_t x,
+                                               uint64_t validm, uint64_t hx, uint64_t V, uint64_t hprev, uint32_t lp,
+                                               uint32_t* err)
+{
+    const uint64_t C = hx << 1;                 // bit x: bond (x-1) -> x
+    const uint64_t S = ~C & validm;             // first sites of runs
+    const uint32_t ri = lanes_below(S >> 1);    // number of run starts in 1..x = run index of x
+    const uint32_t fresh = r * TX + x;
+    // lanes talk through the slots, so these accesses must not be folded away
+    if (lane_in(S)) lds_st(&rl[ri], fresh);
+    if (lane_in(V)) lds_st(&rl[ri], lp);
+    const uint32_t lab = lds_ld(&rl[ri]);
+    if (lane_in(S) && lab == fresh) lds_st(&P[fresh], fresh);
+    // bonds x-1 and x from the same run above into the same run here add nothing
+    const uint64_t R = V & (V << 1) & C & (hprev << 1);
+    enqueue(uq, lane_in(V & ~R) && lp != lab, lp, lab, P, x, err);
+    return lab;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // Bonds + tile-local labels (+ measurement of the incoming configuration).
-// flags bit 0: also measure the configuration the bonds are drawn on (it is
-// the result of the previous sweep, t - 1).
+//
+// Each wave owns a strip of TY/4 consecutive rows and labels it two rows at a
+// time; strips are then stitched along their seams through the same LDS
+// union-find, which always hangs the larger label under the smaller, so the
+// final label of every tile-local cluster is its smallest site.
+//
+// Random words: with L even, one Philox call serves the pair of sites
+// (2m, 2m+1) of one row; lane 2m draws for row r and lane 2m+1 for row r+1,
+// and the two lanes swap the halves the other one needs.
+//
+// flags bit 0: also measure the configuration the bonds are drawn on (the
+// result of the previous sweep, t - 1).
 template <int TY>
 __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const WorkItem* map, uint32_t k,
                                                    uint32_t flags)
 {
-    constexpr uint32_t RPW = TY / 4;   // rows per wave
-    __shared__ uint32_t P[TY * TX];
-    __shared__ uint64_t rb[TY][4];     // per row: +x bonds (2 words), +y bonds (2 words)
+    constexpr uint32_t RPW = TY / 4;   // rows per wave (even)
+    __shared__ uint32_t P[TY * TX];    // union-find over provisional labels
+    __shared__ __align__(16) uint8_t sp[(TY + 1) * SPW];
+    __shared__ uint64_t rb[TY][2];     // per row: +x bond word, +y bond word
+    __shared__ uint32_t RL[4][64];     // per wave: the label of every run of a row
+    __shared__ uint32_t seam[4][64];   // labels of each strip's last row
+    __shared__ uint32_t UQ[4][QCAP];   // per wave: pending unions
     __shared__ uint32_t hist[256];
     __shared__ uint32_t tot[2];
 
@@ -233,107 +356,129 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
 
     hist[tid] = 0;
     if (tid < 2) tot[tid] = 0;
+    stage_spins<TY>(sp, d, g, tid);
     __syncthreads();
 
-    const uint32_t xa = 2 * lane, xb = xa + 1;
-    const bool va = xa < w, vb = xb < w;
-    const uint32_t xh = (x0 + w == L) ? 0u : x0 + w;   // right halo column
+    const uint32_t x = lane;
+    const bool vx = x < w;
+    const uint64_t validm = (w == 64) ? ~0ull : ((1ull << w) - 1ull);
+    const uint64_t cross = 1ull << (w - 1);   // the +x bond of column w-1 leaves the tile
     const uint32_t r0 = wave * RPW, r1 = min(h, r0 + RPW);
+    const bool on = d.thr_nz != 0;
+    const bool even_L = (L & 1u) == 0;
+    uint32_t* rl = RL[wave];
+    UnionQueue uq{UQ[wave], 0u};
     uint32_t n_unsat = 0, n_active = 0;
+    uint32_t prov[RPW];
+    uint32_t lp = 0;
+    uint64_t hprev = 0, vprev = 0;
 
-    if (r0 < r1) {
-        uint32_t y = y0 + r0;
-        size_t base = (size_t)y * L;
-        RowSpins cur = load_row(d.s, base, x0, xa, va, vb, xh);
-        for (uint32_t r = r0; r < r1; ++r) {
-            const uint32_t yn = (r + 1 < h) ? y + 1 : ((y0 + h == L) ? 0u : y0 + h);
-            const size_t nbase = (size_t)yn * L;
-            const RowSpins nxt = load_row(d.s, nbase, x0, xa, va, vb, xh);
+#pragma unroll
+    for (uint32_t i = 0; i < RPW; i += 2) {
+        const uint32_t r = r0 + i;
+        prov[i] = 0;
+        prov[i + 1] = 0;
+        if (r >= r1) continue;
+        const bool two = r + 1 < r1;
+        const uint8_t* row = sp + r * SPW;
+        const uint32_t s0 = row[x], s0r = row[x + 1];
+        const uint32_t s1 = row[SPW + x], s1r = row[SPW + x + 1];
+        const uint32_t s2 = two ? row[2 * SPW + x] : 0u;
 
-            const uint32_t s_next = __shfl_down(cur.a, 1);
-            const uint32_t right_a = vb ? cur.b : cur.halo;
-            const uint32_t right_b = (xb + 1 < w) ? s_next : cur.halo;
-
-            // Philox words: one call covers the pair (2m, 2m+1) of site indices.
-            const uint32_t site_a = (uint32_t)(base + x0 + xa);
-            uint32_t wxa, wya, wxb, wyb;
-            if (((base + x0) & 1u) == 0) {
-                const u32x4 r4 = philox4x32_10(site_a >> 1, 0u, t, 0u, d.key0, d.key1);
-                wxa = r4.x; wya = r4.y; wxb = r4.z; wyb = r4.w;
-            } else {
-                const u32x4 p4 = philox4x32_10(site_a >> 1, 0u, t, 0u, d.key0, d.key1);
-                const u32x4 n4 = philox4x32_10((site_a >> 1) + 1u, 0u, t, 0u, d.key0, d.key1);
-                wxa = p4.z; wya = p4.w; wxb = n4.x; wyb = n4.y;
+        const size_t base0 = (size_t)(y0 + r) * L + x0;
+        uint32_t wx0, wy0, wx1, wy1;
+        if (even_L) {
+            const bool odd = x & 1u;
+            const uint32_t pair = (uint32_t)(((odd ? base0 + L : base0) + (x & ~1u)) >> 1);
+            const u32x4 q4 = philox4x32_10(pair, 0u, t, 0u, d.key0, d.key1);
+            const uint32_t recv0 = swap_pair(odd ? q4.x : q4.z);
+            const uint32_t recv1 = swap_pair(odd ? q4.y : q4.w);
+            wx0 = odd ? recv0 : q4.x;
+            wy0 = odd ? recv1 : q4.y;
+            wx1 = odd ? q4.z : recv0;
+            wy1 = odd ? q4.w : recv1;
+        } else {
+            const uint32_t ga = (uint32_t)(base0 + x), gb = (uint32_t)(base0 + L + x);
+            const u32x4 qa = philox4x32_10(ga >> 1, 0u, t, 0u, d.key0, d.key1);
+            const u32x4 qb = philox4x32_10(gb >> 1, 0u, t, 0u, d.key0, d.key1);
+            wx0 = (ga & 1u) ? qa.z : qa.x;
+            wy0 = (ga & 1u) ? qa.w : qa.y;
+            wx1 = (gb & 1u) ? qb.z : qb.x;
+            wy1 = (gb & 1u) ? qb.w : qb.y;
+        }
+        const bool ex0 = s0 == s0r, ey0 = s0 == s1, ex1 = s1 == s1r, ey1 = s1 == s2;
+        const uint64_t BX0 = ballot(vx && ex0 && on && wx0 <= d.thr_m1);
+        const uint64_t BY0 = ballot(vx && ey0 && on && wy0 <= d.thr_m1);
+        uint64_t BX1 = 0, BY1 = 0;
+        if (two) {
+            BX1 = ballot(vx && ex1 && on && wx1 <= d.thr_m1);
+            BY1 = ballot(vx && ey1 && on && wy1 <= d.thr_m1);
+        }
+        if (lane == 0) {
+            rb[r][0] = BX0;
+            rb[r][1] = BY0;
+            if (two) {
+                rb[r + 1][0] = BX1;
+                rb[r + 1][1] = BY1;
             }
-            const bool exa = cur.a == right_a, eya = cur.a == nxt.a;
-            const bool exb = cur.b == right_b, eyb = cur.b == nxt.b;
-            const bool on = d.thr_nz != 0;
-            const bool bxa = va && exa && on && wxa <= d.thr_m1;
-            const bool bya = va && eya && on && wya <= d.thr_m1;
-            const bool bxb = vb && exb && on && wxb <= d.thr_m1;
-            const bool byb = vb && eyb && on && wyb <= d.thr_m1;
-            uint64_t bx0, bx1, by0, by1;
-            interleave_row(ballot(bxa), ballot(bxb), bx0, bx1);
-            interleave_row(ballot(bya), ballot(byb), by0, by1);
-            if (lane == 0) {
-                rb[r][0] = bx0; rb[r][1] = bx1; rb[r][2] = by0; rb[r][3] = by1;
-                uint64_t* px = d.bonds + (size_t)y * d.W + 2 * g.tx;
-                uint64_t* py = d.bonds + ((size_t)L + y) * d.W + 2 * g.tx;
-                px[0] = bx0;
-                py[0] = by0;
-                if (w > 64) {
-                    px[1] = bx1;
-                    py[1] = by1;
+        }
+
+        const uint64_t hx0 = BX0 & ~cross;
+        const uint32_t lab0 = row_labels(P, rl, uq, r, x, validm, hx0, vprev, hprev, lp, d.err);
+        prov[i] = lab0;
+        lp = lab0;
+        hprev = hx0;
+        vprev = BY0;
+        if (two) {
+            const uint64_t hx1 = BX1 & ~cross;
+            const uint32_t lab1 = row_labels(P, rl, uq, r + 1, x, validm, hx1, vprev, hprev, lp, d.err);
+            prov[i + 1] = lab1;
+            lp = lab1;
+            hprev = hx1;
+            vprev = BY1;
+        }
+
+        if (meas) {
+            n_active += popc64(BX0) + popc64(BY0) + popc64(BX1) + popc64(BY1);
+            if (meas_prev) {
+                n_unsat += popc64(ballot(vx && !ex0)) + popc64(ballot(vx && !ey0));
+                count_states(hist, d.q, lane, vx, s0);
+                if (two) {
+                    n_unsat += popc64(ballot(vx && !ex1)) + popc64(ballot(vx && !ey1));
+                    count_states(hist, d.q, lane, vx, s1);
                 }
             }
-
-            // Runs of +x bonds inside the tile: each site starts out labelled by
-            // the first site of its run (the crossing bond at w-1 is left out).
-            uint64_t hx0 = bx0, hx1 = bx1;
-            if (w <= 64) hx0 &= ~(1ull << (w - 1));
-            else hx1 &= ~(1ull << (w - 65));
-            const uint64_t S0 = ~(hx0 << 1);
-            const uint64_t S1 = ~((hx1 << 1) | (hx0 >> 63));
-            uint32_t st_a;
-            bool link_ab;
-            if (xa < 64) {
-                st_a = msb64(S0 & upto(xa));
-                link_ab = (hx0 >> xa) & 1ull;
-            } else {
-                const uint64_t m = S1 & upto(xa - 64);
-                st_a = m ? 64u + msb64(m) : msb64(S0);
-                link_ab = (hx1 >> (xa - 64)) & 1ull;
-            }
-            const uint32_t st_b = link_ab ? st_a : xb;
-            P[r * TX + xa] = r * TX + st_a;
-            P[r * TX + xb] = r * TX + st_b;
-
-            if (meas) {
-                n_active += popc64(bx0) + popc64(bx1) + popc64(by0) + popc64(by1);
-                if (meas_prev) {
-                    n_unsat += popc64(ballot(va && !exa)) + popc64(ballot(va && !eya)) +
-                               popc64(ballot(vb && !exb)) + popc64(ballot(vb && !eyb));
-                    count_states(hist, d.q, lane, va, vb, cur.a, cur.b);
-                }
-            }
-            cur = nxt;
-            base = nbase;
-            y = yn;
         }
     }
+    seam[wave][lane] = lp;
     if (meas && lane == 0) {
         atomicAdd(&tot[0], n_unsat);
         atomicAdd(&tot[1], n_active);
     }
     __syncthreads();
 
-    // Tile edge record: crossing-bond masks.
+    // Seams: +y bonds from the last row of the strip above into this strip.
+    if (wave > 0 && r0 < h) {
+        const uint32_t ru = r0 - 1;
+        const uint64_t V = rb[ru][1];
+        const uint64_t hu = rb[ru][0] & ~cross, hc = rb[r0][0] & ~cross;
+        const uint64_t R = V & (V << 1) & (hc << 1) & (hu << 1);
+        const uint32_t up = seam[wave - 1][lane];
+        enqueue(uq, lane_in(V & ~R) && up != prov[0], up, prov[0], P, lane, d.err);
+    }
+    drain(uq, P, lane, d.err);
+
+    // Tile record: bond words (tile-major), crossing-bond masks.
     uint32_t* rec = d.edges + (size_t)tile * edge_words(TY);
+    uint64_t* bw = d.bonds + (size_t)tile * 2 * TY;
+    for (uint32_t j = tid; j < 2 * TY; j += 256) {
+        const uint32_t r = j % TY;
+        if (r < h) bw[j] = rb[r][j / TY];
+    }
     if (wave == 0) {
         for (uint32_t j = 0; j < TY; j += 64) {
             const uint32_t r = j + lane;
-            bool bit = false;
-            if (r < h) bit = (w <= 64) ? ((rb[r][0] >> (w - 1)) & 1ull) : ((rb[r][1] >> (w - 65)) & 1ull);
+            const bool bit = r < h && ((rb[r][0] >> (w - 1)) & 1ull);
             const uint64_t m = ballot(bit);
             if (lane == 0) {
                 rec[j / 32] = (uint32_t)m;
@@ -345,56 +490,26 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
                 rec[2] = 0;
                 rec[3] = 0;
             }
-            const uint64_t b0 = rb[h - 1][2], b1 = rb[h - 1][3];
-            rec[4] = (uint32_t)b0;
-            rec[5] = (uint32_t)(b0 >> 32);
-            rec[6] = (uint32_t)b1;
-            rec[7] = (uint32_t)(b1 >> 32);
+            const uint64_t b = rb[h - 1][1];
+            rec[4] = (uint32_t)b;
+            rec[5] = (uint32_t)(b >> 32);
         }
-    }
-
-    // Vertical links between consecutive rows of the tile, skipping those that
-    // join two runs already joined one column to the left.
-    for (uint32_t r = r0; r < r1 && r + 1 < h; ++r) {
-        uint64_t vy0 = rb[r][2], vy1 = rb[r][3];
-        uint64_t h0 = rb[r][0], h1 = rb[r][1], n0 = rb[r + 1][0], n1 = rb[r + 1][1];
-        if (w <= 64) {
-            h0 &= ~(1ull << (w - 1));
-            n0 &= ~(1ull << (w - 1));
-        } else {
-            h1 &= ~(1ull << (w - 65));
-            n1 &= ~(1ull << (w - 65));
-        }
-        const uint64_t red0 = (vy0 << 1) & (h0 << 1) & (n0 << 1);
-        const uint64_t red1 = ((vy1 << 1) | (vy0 >> 63)) & ((h1 << 1) | (h0 >> 63)) & ((n1 << 1) | (n0 >> 63));
-        const uint64_t u0 = vy0 & ~red0, u1 = vy1 & ~red1;
-        const uint64_t word = (xa < 64) ? u0 : u1;
-        const uint32_t sh = xa & 63u;
-        if ((word >> sh) & 1ull) lds_union(P, r * TX + xa, (r + 1) * TX + xa, d.err);
-        if ((word >> (sh + 1)) & 1ull) lds_union(P, r * TX + xb, (r + 1) * TX + xb, d.err);
     }
     __syncthreads();
 
     // Final tile-local labels as global site indices.
-    for (uint32_t r = r0; r < r1; ++r) {
-        const size_t row = (size_t)(y0 + r) * L + x0;
-        const uint32_t la = lds_find(P, r * TX + xa, d.err);
-        const uint32_t lb = lds_find(P, r * TX + xb, d.err);
-        const uint32_t ga = (uint32_t)((size_t)(y0 + (la >> 7)) * L + x0 + (la & 127u));
-        const uint32_t gb = (uint32_t)((size_t)(y0 + (lb >> 7)) * L + x0 + (lb & 127u));
-        if (va) d.lab[row + xa] = ga;
-        if (vb) d.lab[row + xb] = gb;
-        if (va && xa == w - 1) rec[8 + r] = ga;
-        if (vb && xb == w - 1) rec[8 + r] = gb;
-        if (lane == 0) rec[8 + TY + r] = ga;
-        if (r == h - 1) {
-            if (va) rec[8 + 2 * TY + xa] = ga;
-            if (vb) rec[8 + 2 * TY + xb] = gb;
-        }
-        if (r == 0) {
-            if (va) rec[8 + 2 * TY + TX + xa] = ga;
-            if (vb) rec[8 + 2 * TY + TX + xb] = gb;
-        }
+#pragma unroll
+    for (uint32_t i = 0; i < RPW; ++i) {
+        const uint32_t r = r0 + i;
+        if (r >= r1) continue;
+        // provisional labels exist only for sites inside the tile
+        const uint32_t la = vx ? lds_find(P, prov[i], d.err) : 0u;
+        const uint32_t ga = (uint32_t)((size_t)(y0 + la / TX) * L + x0 + la % TX);
+        if (vx) d.lab[(size_t)(y0 + r) * L + x0 + x] = ga;
+        if (vx && x == w - 1) rec[8 + r] = ga;
+        if (x == 0) rec[8 + TY + r] = ga;
+        if (vx && r == h - 1) rec[8 + 2 * TY + x] = ga;
+        if (vx && r == 0) rec[8 + 2 * TY + TX + x] = ga;
     }
 
     if (meas) {
@@ -422,6 +537,7 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
     if (!pick(descs, map, idx, false, d, tile)) return;
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t EW = edge_words(TY);
+    const uint64_t N = (uint64_t)d.L * d.L;
     const uint32_t t_right = g.ty * d.ntx + ((g.tx + 1 == d.ntx) ? 0u : g.tx + 1);
     const uint32_t t_below = ((g.ty + 1 == d.nty) ? 0u : g.ty + 1) * d.ntx + g.tx;
     const uint32_t* rec = d.edges + (size_t)tile * EW;
@@ -446,13 +562,11 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
         pa = __shfl(a, 63);
         pb = __shfl(b, 63);
         // consecutive crossing bonds between the same two clusters: join once
-        if (bit && !(ua == a && ub == b)) g_unite(d.lab, (uint64_t)d.L * d.L, a, b, d.err);
+        if (bit && !(ua == a && ub == b)) g_unite(d.lab, N, a, b, d.err);
     }
     // Bottom edge: column x joins (x, h-1) here with (x, 0) of the tile below.
-    pa = INVALID;
-    pb = INVALID;
-    for (uint32_t j = 0; j < TX; j += 64) {
-        const uint32_t x = j + lane;
+    {
+        const uint32_t x = lane;
         const bool bit = x < g.w && ((rec[4 + (x >> 5)] >> (x & 31u)) & 1u);
         uint32_t a = INVALID, b = INVALID;
         if (bit) {
@@ -461,12 +575,10 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
         }
         uint32_t ua = __shfl_up(a, 1), ub = __shfl_up(b, 1);
         if (lane == 0) {
-            ua = pa;
-            ub = pb;
+            ua = INVALID;
+            ub = INVALID;
         }
-        pa = __shfl(a, 63);
-        pb = __shfl(b, 63);
-        if (bit && !(ua == a && ub == b)) g_unite(d.lab, (uint64_t)d.L * d.L, a, b, d.err);
+        if (bit && !(ua == a && ub == b)) g_unite(d.lab, N, a, b, d.err);
     }
 }
 
@@ -474,11 +586,13 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
 // Flip: every site takes the state drawn for the smallest site index of its
 // cluster.  Inside the tile the labels form a forest whose terminals are the
 // sites that are global roots or whose parent lies outside the tile; only the
-// terminals search the global forest and draw a state, in compacted lanes.
+// terminals search the global forest (compressing the paths they walk) and
+// draw a state, in compacted lanes.  Thread t owns the sites of column
+// t mod 64 in rows t/64, t/64 + 4, ...; their labels are all loaded first.
 template <int TY>
 __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkItem* map, uint32_t k)
 {
-    constexpr uint32_t RPW = TY / 4;
+    constexpr uint32_t PER = TY / 4;   // sites per thread
     __shared__ uint32_t E[TY * TX];
     __shared__ uint16_t list[TY * TX];
     __shared__ uint32_t nlist;
@@ -488,44 +602,45 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
     if (!pick(descs, map, blockIdx.x, true, d, tile)) return;
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t t = *d.counter + k;
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
     const uint32_t L = d.L, w = g.w, h = g.h, x0 = g.x0, y0 = g.y0;
-    const uint32_t xa = 2 * lane, xb = xa + 1;
-    const bool va = xa < w, vb = xb < w;
-    const uint32_t r0 = wave * RPW, r1 = min(h, r0 + RPW);
+    const uint32_t col = lane, rr = tid >> 6;
+    const bool vcol = col < w;
 
     if (tid == 0) nlist = 0;
+    uint32_t v[PER];
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+        const uint32_t r = rr + 4 * j;
+        v[j] = (vcol && r < h) ? d.lab[(size_t)(y0 + r) * L + x0 + col] : 0u;
+    }
     __syncthreads();
 
-    for (uint32_t r = r0; r < r1; ++r) {
-        const size_t row = (size_t)(y0 + r) * L + x0;
 #pragma unroll
-        for (uint32_t part = 0; part < 2; ++part) {
-            const uint32_t x = part ? xb : xa;
-            const bool valid = part ? vb : va;
-            const uint32_t li = r * TX + x;
-            bool term = false;
-            if (valid) {
-                const uint32_t gi = (uint32_t)(row + x);
-                const uint32_t v = d.lab[gi];
-                term = true;
-                if (v != gi) {
-                    const uint32_t vy = div_L(d, v);
-                    const uint32_t dy = vy - y0, dx = (v - vy * L) - x0;
-                    if (dy < h && dx < w) {
-                        E[li] = dy * TX + dx;
-                        term = false;
-                    }
+    for (uint32_t j = 0; j < PER; ++j) {
+        const uint32_t r = rr + 4 * j;
+        const bool valid = vcol && r < h;
+        const uint32_t li = r * TX + col;
+        bool term = false;
+        if (valid) {
+            const uint32_t gi = (uint32_t)((size_t)(y0 + r) * L + x0 + col);
+            term = true;
+            if (v[j] != gi) {
+                const uint32_t vy = div_L(d, v[j]);
+                const uint32_t dy = vy - y0, dx = (v[j] - vy * L) - x0;
+                if (dy < h && dx < w) {
+                    E[li] = dy * TX + dx;
+                    term = false;
                 }
-                if (term) E[li] = v;
             }
-            const uint64_t m = ballot(term);
-            if (m) {
-                uint32_t at = 0;
-                if (lane == 0) at = atomicAdd(&nlist, popc64(m));
-                at = __shfl(at, 0);
-                if (term) list[at + popc64(m & ((1ull << lane) - 1ull))] = (uint16_t)li;
-            }
+            if (term) E[li] = v[j];
+        }
+        const uint64_t m = ballot(term);
+        if (m) {
+            uint32_t at = 0;
+            if (lane == 0) at = atomicAdd(&nlist, popc64(m));
+            at = __shfl(at, 0);
+            if (term) list[at + lanes_below(m)] = (uint16_t)li;
         }
     }
     __syncthreads();
@@ -533,27 +648,26 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
     const uint32_t n = nlist;
     for (uint32_t j = tid; j < n; j += 256) {
         const uint32_t li = list[j];
-        const uint32_t v = E[li];
+        const uint32_t vv = E[li];
         const uint32_t gi = (uint32_t)((size_t)(y0 + li / TX) * L + x0 + li % TX);
-        uint32_t root = v;
-        if (v != gi) {
-            if (v < gi) root = g_root(d.lab, v, d.err);
+        uint32_t root = vv;
+        if (vv != gi) {
+            if (vv < gi) root = g_root_compress(d.lab, vv, d.err);
             else flag_error(d.err);
         }
         E[li] = TERM | cluster_state(d, root, t);
     }
     __syncthreads();
 
-    for (uint32_t r = r0; r < r1; ++r) {
-        const size_t row = (size_t)(y0 + r) * L + x0;
-        uint32_t ea = va ? E[r * TX + xa] : TERM;
-        uint32_t eb = vb ? E[r * TX + xb] : TERM;
-        // in-tile pointers strictly decrease, so these chases end
-        for (uint32_t it = 0; it < LDS_CAP && !(ea & TERM); ++it) ea = E[ea];
-        for (uint32_t it = 0; it < LDS_CAP && !(eb & TERM); ++it) eb = E[eb];
-        if (!(ea & eb & TERM)) flag_error(d.err);
-        if (va) d.s[row + xa] = (uint8_t)ea;
-        if (vb) d.s[row + xb] = (uint8_t)eb;
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+        const uint32_t r = rr + 4 * j;
+        if (!(vcol && r < h)) continue;
+        uint32_t e = E[r * TX + col];
+        // in-tile pointers strictly decrease, so this chase ends
+        for (uint32_t it = 0; it < LDS_CAP && !(e & TERM); ++it) e = E[e];
+        if (!(e & TERM)) flag_error(d.err);
+        d.s[(size_t)(y0 + r) * L + x0 + col] = (uint8_t)e;
     }
 
     // The ring record of the next sweep starts from zero.
@@ -571,6 +685,7 @@ __global__ __launch_bounds__(256) void k_measure(const LatDesc* descs, const Wor
                                                 const uint32_t* n_each)
 {
     constexpr uint32_t RPW = TY / 4;
+    __shared__ __align__(16) uint8_t sp[(TY + 1) * SPW];
     __shared__ uint32_t hist[256];
     __shared__ uint32_t tot;
     LatDesc d;
@@ -585,33 +700,20 @@ __global__ __launch_bounds__(256) void k_measure(const LatDesc* descs, const Wor
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t t = *d.counter + k;
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
-    const uint32_t L = d.L, w = g.w, h = g.h, x0 = g.x0, y0 = g.y0;
+    const uint32_t w = g.w, h = g.h;
     hist[tid] = 0;
     if (tid == 0) tot = 0;
+    stage_spins<TY>(sp, d, g, tid);
     __syncthreads();
-    const uint32_t xa = 2 * lane, xb = xa + 1;
-    const bool va = xa < w, vb = xb < w;
-    const uint32_t xh = (x0 + w == L) ? 0u : x0 + w;
+    const uint32_t x = lane;
+    const bool vx = x < w;
     const uint32_t r0 = wave * RPW, r1 = min(h, r0 + RPW);
     uint32_t n_unsat = 0;
-    if (r0 < r1) {
-        uint32_t y = y0 + r0;
-        size_t base = (size_t)y * L;
-        RowSpins cur = load_row(d.s, base, x0, xa, va, vb, xh);
-        for (uint32_t r = r0; r < r1; ++r) {
-            const uint32_t yn = (r + 1 < h) ? y + 1 : ((y0 + h == L) ? 0u : y0 + h);
-            const size_t nbase = (size_t)yn * L;
-            const RowSpins nxt = load_row(d.s, nbase, x0, xa, va, vb, xh);
-            const uint32_t s_next = __shfl_down(cur.a, 1);
-            const uint32_t right_a = vb ? cur.b : cur.halo;
-            const uint32_t right_b = (xb + 1 < w) ? s_next : cur.halo;
-            n_unsat += popc64(ballot(va && cur.a != right_a)) + popc64(ballot(va && cur.a != nxt.a)) +
-                       popc64(ballot(vb && cur.b != right_b)) + popc64(ballot(vb && cur.b != nxt.b));
-            count_states(hist, d.q, lane, va, vb, cur.a, cur.b);
-            cur = nxt;
-            base = nbase;
-            y = yn;
-        }
+    for (uint32_t r = r0; r < r1; ++r) {
+        const uint8_t* row = sp + r * SPW;
+        const uint32_t s = row[x], sr = row[x + 1], sd = row[SPW + x];
+        n_unsat += popc64(ballot(vx && s != sr)) + popc64(ballot(vx && s != sd));
+        count_states(hist, d.q, lane, vx, s);
     }
     if (lane == 0) atomicAdd(&tot, n_unsat);
     __syncthreads();
@@ -663,12 +765,12 @@ uint32_t init_grid(size_t N)
 }
 }  // namespace
 
-#define SWMI_TY_DISPATCH(TYV, KERNEL, GRID, ...)                                                  \
-    switch (TYV) {                                                                                \
-    case 32: hipLaunchKernelGGL(KERNEL<32>, dim3(GRID), dim3(256), 0, w.stream, __VA_ARGS__); break;  \
-    case 64: hipLaunchKernelGGL(KERNEL<64>, dim3(GRID), dim3(256), 0, w.stream, __VA_ARGS__); break;  \
+#define SWMI_TY_DISPATCH(TYV, KERNEL, GRID, ...)                                                       \
+    switch (TYV) {                                                                                     \
+    case 32: hipLaunchKernelGGL(KERNEL<32>, dim3(GRID), dim3(256), 0, w.stream, __VA_ARGS__); break;   \
+    case 64: hipLaunchKernelGGL(KERNEL<64>, dim3(GRID), dim3(256), 0, w.stream, __VA_ARGS__); break;   \
     case 128: hipLaunchKernelGGL(KERNEL<128>, dim3(GRID), dim3(256), 0, w.stream, __VA_ARGS__); break; \
-    default: return hipErrorInvalidValue;                                                         \
+    default: return hipErrorInvalidValue;                                                              \
     }
 
 hipError_t launch_bond_label(const Work& w, uint32_t k, uint32_t flags)

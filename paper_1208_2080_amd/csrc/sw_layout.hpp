@@ -1,23 +1,25 @@
 // Data layout of one lattice in device memory, shared by kernels and host runtime.
 //
-// Per lattice (all arrays row-major, site i = y*L + x):
+// Per lattice (site i = y*L + x, row-major):
 //   spins   uint8  [N]
 //   labels  uint32 [N]        after a sweep: non-root sites hold the smallest
 //                             site index of their tile-local cluster; tile-local
 //                             roots hold their parent in the global forest
-//   bonds   uint64 [2][L][W]  W = ceil(L/64); +x plane then +y plane
+//   bonds   uint64 [tiles][2][TY]  tile-major bond words: tile t, plane p (0: +x,
+//                             1: +y), row r; bit x = bond of site (x0 + x, y0 + r)
 //   edges   uint32 [tiles][EDGE_WORDS(TY)]  per-tile boundary record (below)
-//   ring    int64  [cap][NCOPY][q+1]  per-sweep sums: n_unsat, n_active,
+//   ring    int64  [slots][NCOPY][q+1]  per-sweep sums: n_unsat, n_active,
 //                             n_1..n_{q-1} (n_0 = N - the rest), NCOPY partial
 //                             copies to spread atomic traffic
-//   counter uint32            sweeps done
+//   state   DevState          sweep counter and error flag
+// Tiles are TX = 64 columns by TY rows (TY = 32, 64 or 128), numbered row-major.
 #pragma once
 
 #include <stdint.h>
 
 namespace swmi {
 
-constexpr uint32_t TX = 128;          // tile width: one wave, two sites per lane
+constexpr uint32_t TX = 64;           // tile width: one wave, one column per lane
 constexpr uint32_t NCOPY = 16;        // partial copies of each ring record
 constexpr uint32_t TERM = 0x80000000u;
 constexpr uint32_t CAP_STEPS = 1u << 26;  // safety cap on any pointer-chasing loop
@@ -25,7 +27,8 @@ constexpr uint32_t INVALID = 0xFFFFFFFFu;
 
 // Boundary record of a tile with TY rows (uint32 words):
 //   [0, 4)            right-edge crossing bonds, bit r = +x bond of (w-1, r)
-//   [4, 8)            bottom-edge crossing bonds, bit x = +y bond of (x, h-1)
+//   [4, 6)            bottom-edge crossing bonds, bit x = +y bond of (x, h-1)
+//   [6, 8)            unused
 //   [8, 8+TY)         labels of the right column
 //   [8+TY, 8+2TY)     labels of the left column
 //   [8+2TY, +TX)      labels of the bottom row
@@ -53,7 +56,7 @@ struct LatDesc {
     uint32_t thr_nz;       // threshold != 0
     uint32_t key0, key1;
     uint32_t magic, shift; // division by L
-    uint32_t pad0;
+    uint32_t log2L;        // log2 L when L is a power of two, else 0
 };
 
 // Block-to-work map entry of the batched form: lattice index and tile index.
