@@ -98,6 +98,46 @@ def copy_calibration(nbytes: int = 1 << 30):
     del a, b
 
 
+def batched_vs_plain(n_replicas: int, sweeps: int, tile_rows: int) -> dict:
+    """Aggregate flips/ns of independent replicas of uneven L, q, K swept as one
+    batch (one launch per phase, HIP graph) versus one lattice after another."""
+    import numpy as np
+    import torch
+    from paper_1208_2080_amd import binding
+    from paper_1208_2080_amd import workloads as wl
+
+    reps = wl.batched_replicas(n=n_replicas, sweeps=sweeps)
+    flips = sum(r["L"] ** 2 for r in reps) * sweeps
+    b = binding.Batch(reps, obs_capacity=2, tile_rows=tile_rows)
+    b.sweep_all(2)                                   # warm-up (and graph capture)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < sweeps:
+        n = min(100, sweeps - done)
+        b.sweep_all(n)
+        done += n
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    lats = [binding.Lattice(r["L"], r["q"], r["K"], seed=r["seed"], obs_capacity=2, tile_rows=tile_rows)
+            for r in reps]
+    for lat in lats:
+        lat.sweep(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for lat in lats:
+        lat.sweep(sweeps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    same = all(np.array_equal(b.spins(i), lat.spins()) for i, lat in enumerate(lats))
+    for lat in lats:
+        lat.close()
+    b.close()
+    return {"replicas": n_replicas, "sweeps": sweeps, "sites": flips // sweeps,
+            "batched_flips_per_ns": flips / (t_batch * 1e9), "plain_flips_per_ns": flips / (t_plain * 1e9),
+            "speedup": t_plain / t_batch, "identical_results": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +149,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
+    ap.add_argument("--batched", type=int, default=0, metavar="SWEEPS",
+                    help="also time 256 uneven replicas batched vs one after another for SWEEPS sweeps")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -186,6 +228,9 @@ def main():
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    if args.batched:
+        print("# batched vs plain", file=sys.stderr, flush=True)
+        out["batched_vs_plain"] = batched_vs_plain(256, args.batched, args.tile_rows)
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on one sweep", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)

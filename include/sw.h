@@ -138,7 +138,9 @@ int sw_batch_init(const sw_params* params, uint32_t n, void* dev_ws, size_t ws_b
 /* Sweep replica r n_sweeps[r] times (0 = leave it alone); asynchronous. */
 int sw_batch_sweep(sw_batch* b, const uint32_t* n_sweeps);
 
-/* Same sweep count for every replica, n times over (captured as a HIP graph). */
+/* Same sweep count for every replica (captured once per count as a HIP graph
+ * and replayed; on the legacy NULL stream, which cannot be captured, the
+ * kernels are launched directly). */
 int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps);
 
 int sw_batch_measure(sw_batch* b, uint32_t replica, uint32_t first, uint32_t n, int64_t* host_out);

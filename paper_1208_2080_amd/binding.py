@@ -223,8 +223,10 @@ class Batch:
         nbytes = ctypes.c_size_t()
         _check(lib().sw_batch_workspace_bytes(arr, n, ctypes.byref(nbytes)))
         self.device = torch.device("cuda", 0) if device is None else torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a stream of its own (default priority): HIP graphs cannot capture the NULL stream
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()   # workspace allocated before first use
         self._h = ctypes.c_void_p()
         _check(lib().sw_batch_init(arr, n, ctypes.c_void_p(self.ws.data_ptr()), nbytes.value,
                                    ctypes.c_void_p(_stream_handle(self.stream)), ctypes.byref(self._h)))

@@ -667,6 +667,13 @@ int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps)
         if ((uint64_t)b->done[r] + n_sweeps > 0xFFFFFFFFull)
             return fail(SW_ESTATE, "replica %u: sweep counter would overflow", r);
     std::vector<uint32_t> all(b->n, n_sweeps);
+    if (b->stream == nullptr) {
+        // the legacy default stream cannot be captured: launch directly
+        const int rc = batch_enqueue(b, all.data());
+        if (rc) return rc;
+        for (uint32_t r = 0; r < b->n; ++r) b->done[r] += n_sweeps;
+        return SW_OK;
+    }
     auto it = b->graphs.find(n_sweeps);
     // the graph bakes in the work map of "every replica"; make sure it is the one uploaded
     std::vector<uint32_t> order(b->n);

@@ -87,16 +87,8 @@ __device__ __forceinline__ uint64_t upto(uint32_t b) { return (2ull << b) - 1ull
 __device__ __forceinline__ uint32_t msb64(uint64_t v) { return 63u - (uint32_t)__clzll(v); }
 
 // ------------------------------------------------------- coherent access
-// Labels are shared between workgroups on different XCDs while the merge runs,
-// so every access there goes through device-coherent atomics.
-__device__ __forceinline__ uint32_t ld_coherent(const uint32_t* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_coherent(uint32_t* p, uint32_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// Labels are hooked by workgroups on different XCDs while the merge runs, so
+// the hook is a device-coherent atomic.
 __device__ __forceinline__ uint32_t min_coherent(uint32_t* p, uint32_t v)
 {
     return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -129,16 +129,21 @@ __device__ void lds_union(uint32_t* P, uint32_t a, uint32_t b, uint32_t* err)
 }
 
 // ---------------------------------------------------- global union-find
+// The finds read through the caches.  A stale value is a parent the node had
+// earlier, still a smaller index in the same cluster, so chases still end and
+// only ever reach true ancestors or stale roots; the hook itself is a
+// device-coherent atomicMin that returns the current parent, and a hook on a
+// stale root retries from that value.  Hence the forest stays exact.
 __device__ uint32_t g_find(uint32_t* lab, uint32_t x, uint32_t* err)
 {
     for (uint32_t it = 0; it < FIND_CAP; ++it) {
-        const uint32_t p = ld_coherent(&lab[x]);
+        const uint32_t p = lab[x];
         if (p == x) return x;
         if (p > x) break;
-        const uint32_t gp = ld_coherent(&lab[p]);
+        const uint32_t gp = lab[p];
         if (gp == p) return p;
         if (gp > p) break;
-        st_coherent(&lab[x], gp);
+        lab[x] = gp;
         x = gp;
     }
     flag_error(err);
