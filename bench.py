@@ -138,6 +138,31 @@ def batched_vs_plain(n_replicas: int, sweeps: int, tile_rows: int) -> dict:
             "speedup": t_plain / t_batch, "identical_results": bool(same)}
 
 
+def serving(n_jobs: int, capacity_flips_per_ns: float, tile_rows: int, loads=(0.5, 0.9, 1.2)) -> list:
+    """The continuous-batching server on Poisson job streams offered at fractions
+    of the measured single-lattice capacity (jobs/s = load x flips/s / mean flips
+    per job), under a 64 GiB HBM budget."""
+    import numpy as np
+    from paper_1208_2080_amd import serve
+    from paper_1208_2080_amd import workloads as wl
+
+    probe = wl.serving_jobs(n=4000)
+    mean_flips = float(np.mean([j["L"] ** 2 * j["sweeps"] for j in probe]))
+    out = []
+    for load in loads:
+        rate = load * capacity_flips_per_ns * 1e9 / mean_flips
+        raw = wl.serving_jobs(n=n_jobs, rate_per_s=rate)
+        jobs = [serve.Job(id=j["id"], L=j["L"], q=j["q"], K=j["K"], seed=j["seed"], sweeps=j["sweeps"],
+                          arrival=j["arrival"]) for j in raw]
+        backend = serve.GpuBackend(max_jobs=128, max_tiles=1 << 20, tile_rows=tile_rows)
+        srv = serve.SwServer(backend, hbm_budget=64 << 30, max_jobs=128, max_tiles=1 << 20, step_sweeps=20)
+        print(f"# serving {n_jobs} jobs at {load:.1f} x capacity ({rate:.2f} jobs/s)", file=sys.stderr, flush=True)
+        _, stats = srv.run(jobs, realtime=True)
+        backend.close()
+        out.append(dict(stats, load=load, offered_jobs_per_s=rate))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -151,6 +176,8 @@ def main():
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--batched", type=int, default=0, metavar="SWEEPS",
                     help="also time 256 uneven replicas batched vs one after another for SWEEPS sweeps")
+    ap.add_argument("--serve", type=int, default=0, metavar="JOBS",
+                    help="also run the server on JOBS Poisson jobs at 0.5, 0.9 and 1.2 x capacity")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -228,6 +255,22 @@ def main():
     lat.close()
     del lat
     torch.cuda.empty_cache()
+    if not args.update_only:
+        # Table 1's other column: the same sweeps with the measurement off
+        lat = binding.Lattice(L, q, K, seed=cfg["seed"], random_start=cfg["random_start"], obs_capacity=0,
+                              tile_rows=args.tile_rows)
+        lat.sweep(args.warmup)
+        torch.cuda.synchronize()
+        n_uo = min(args.steps, 1000)
+        t0 = time.perf_counter()
+        lat.sweep(n_uo)
+        torch.cuda.synchronize()
+        out["update_only_flips_per_ns"] = N * n_uo / ((time.perf_counter() - t0) * 1e9)
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    if args.serve:
+        out["serving"] = serving(args.serve, value, args.tile_rows)
     if args.batched:
         print("# batched vs plain", file=sys.stderr, flush=True)
         out["batched_vs_plain"] = batched_vs_plain(256, args.batched, args.tile_rows)

@@ -57,7 +57,7 @@ __device__ __forceinline__ uint32_t div_L(const LatDesc& d, uint32_t n)
 }
 
 // ----------------------------------------------------------- wave helpers
-__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
 
@@ -86,10 +86,24 @@ __device__ __forceinline__ uint64_t upto(uint32_t b) { return (2ull << b) - 1ull
 
 __device__ __forceinline__ uint32_t msb64(uint64_t v) { return 63u - (uint32_t)__clzll(v); }
 
+// ----------------------------------------------------------- global memory
+// Pointers read from a descriptor have no known address space; accesses
+// through them would compile to flat instructions, which also hold the LDS
+// counter and so make every LDS wait cover outstanding global traffic.
+// All global accesses go through these casts.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> glb(T* p)
+{
+    return (gptr<T>)p;
+}
+
 // ------------------------------------------------------- coherent access
 // Labels are hooked by workgroups on different XCDs while the merge runs, so
 // the hook is a device-coherent atomic.
-__device__ __forceinline__ uint32_t min_coherent(uint32_t* p, uint32_t v)
+__device__ __forceinline__ uint32_t min_coherent(gptr<uint32_t> p, uint32_t v)
 {
     return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

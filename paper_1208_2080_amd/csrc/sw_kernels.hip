@@ -63,7 +63,10 @@ __device__ __forceinline__ bool pick(const LatDesc* descs, const WorkItem* map, 
     return true;
 }
 
-__device__ __forceinline__ void flag_error(uint32_t* err) { atomicOr(err, 1u); }
+__device__ __forceinline__ void flag_error(uint32_t* err)
+{
+    __hip_atomic_fetch_or(glb(err), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 // Lane l's bit of a wave-uniform mask, as a lane predicate.
 __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
@@ -95,7 +98,7 @@ __device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ uint32_t lds_find(uint32_t* P, uint32_t x, uint32_t* err)
+__device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x, uint32_t* err)
 {
     for (uint32_t it = 0; it < LDS_CAP; ++it) {
         const uint32_t p = lds_ld(&P[x]);
@@ -134,7 +137,7 @@ __device__ void lds_union(uint32_t* P, uint32_t a, uint32_t b, uint32_t* err)
 // only ever reach true ancestors or stale roots; the hook itself is a
 // device-coherent atomicMin that returns the current parent, and a hook on a
 // stale root retries from that value.  Hence the forest stays exact.
-__device__ uint32_t g_find(uint32_t* lab, uint32_t x, uint32_t* err)
+__device__ uint32_t g_find(gptr<uint32_t> lab, uint32_t x, uint32_t* err)
 {
     for (uint32_t it = 0; it < FIND_CAP; ++it) {
         const uint32_t p = lab[x];
@@ -150,7 +153,7 @@ __device__ uint32_t g_find(uint32_t* lab, uint32_t x, uint32_t* err)
     return x;
 }
 
-__device__ void g_unite(uint32_t* lab, uint64_t N, uint32_t a, uint32_t b, uint32_t* err)
+__device__ void g_unite(gptr<uint32_t> lab, uint64_t N, uint32_t a, uint32_t b, uint32_t* err)
 {
     if (a >= N || b >= N) {
         flag_error(err);
@@ -165,7 +168,7 @@ __device__ void g_unite(uint32_t* lab, uint64_t N, uint32_t a, uint32_t b, uint3
             a = b;
             b = t;
         }
-        const uint32_t old = min_coherent(&lab[a], b);
+        const uint32_t old = min_coherent(lab + a, b);
         if (old == a) return;
         a = old;
     }
@@ -173,7 +176,7 @@ __device__ void g_unite(uint32_t* lab, uint64_t N, uint32_t a, uint32_t b, uint3
 }
 
 // Read-only root search once the forest is final (after the merge kernel).
-__device__ uint32_t g_root(const uint32_t* lab, uint32_t x, uint32_t* err)
+__device__ uint32_t g_root(gptr<uint32_t> lab, uint32_t x, uint32_t* err)
 {
     for (uint32_t it = 0; it < FIND_CAP; ++it) {
         const uint32_t p = lab[x];
@@ -188,7 +191,7 @@ __device__ uint32_t g_root(const uint32_t* lab, uint32_t x, uint32_t* err)
 // Root search with path compression, once the merge is over: every node on
 // the walked path is pointed straight at the root (a benign race: any value
 // written is an ancestor of the node).
-__device__ uint32_t g_root_compress(uint32_t* lab, uint32_t x, uint32_t* err)
+__device__ uint32_t g_root_compress(gptr<uint32_t> lab, uint32_t x, uint32_t* err)
 {
     const uint32_t root = g_root(lab, x, err);
     for (uint32_t it = 0; it < FIND_CAP && x != root; ++it) {
@@ -218,7 +221,7 @@ __device__ __forceinline__ void stage_spins(uint8_t* sp, const LatDesc& d, const
             const uint32_t r = rr + (tid >> 4);
             if (r <= h && c < dw) {
                 const uint32_t y = (r < h) ? g.y0 + r : yb;
-                const uint32_t v = *reinterpret_cast<const uint32_t*>(d.s + (size_t)y * L + g.x0 + 4 * c);
+                const uint32_t v = *reinterpret_cast<gptr<const uint32_t>>(glb(d.s) + (size_t)y * L + g.x0 + 4 * c);
                 *reinterpret_cast<uint32_t*>(sp + r * SPW + 4 * c) = v;
             }
         }
@@ -229,13 +232,13 @@ __device__ __forceinline__ void stage_spins(uint8_t* sp, const LatDesc& d, const
             const uint32_t r = rr + (tid >> 6);
             if (r <= h && c < w) {
                 const uint32_t y = (r < h) ? g.y0 + r : yb;
-                sp[r * SPW + c] = d.s[(size_t)y * L + g.x0 + c];
+                sp[r * SPW + c] = glb(d.s)[(size_t)y * L + g.x0 + c];
             }
         }
     }
     for (uint32_t r = tid; r <= h; r += 256) {
         const uint32_t y = (r < h) ? g.y0 + r : yb;
-        sp[r * SPW + w] = d.s[(size_t)y * L + xh];
+        sp[r * SPW + w] = glb(d.s)[(size_t)y * L + xh];
     }
 }
 
@@ -255,24 +258,26 @@ __device__ __forceinline__ void count_states(uint32_t* hist, uint32_t q, uint32_
 // Add a workgroup's measurement into a ring record (NCOPY partial copies).
 __device__ __forceinline__ int64_t* ring_record(const LatDesc& d, uint32_t sweep, uint32_t copy)
 {
-    return d.ring + ((size_t)(sweep % d.cap) * NCOPY + copy) * (d.q + 1);
+    return d.ring + ((size_t)(sweep % d.cap) * NCOPY + copy) * (d.q + 1);   // cast at the access
 }
 
 __device__ __forceinline__ void atomic_add_i64(int64_t* p, uint64_t v)
 {
-    atomicAdd(reinterpret_cast<unsigned long long*>(p), (unsigned long long)v);
+    __hip_atomic_fetch_add(glb(reinterpret_cast<unsigned long long*>(p)), (unsigned long long)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Per-wave queue of pending unions (pairs of provisional labels, 16 bits
 // each).  Row labelling never reads the union-find, so unions can wait and
 // then run with every lane busy instead of one lane of a diverged wave.
-constexpr uint32_t QCAP = 256;
+constexpr uint32_t QCAP = 256;   // a two-row step queues at most 128
 
 struct UnionQueue {
     uint32_t* q;   // QCAP slots in LDS
     uint32_t n;    // wave-uniform fill
 };
 
+// Run the queued unions, one per lane.
 __device__ __forceinline__ void drain(UnionQueue& uq, uint32_t* P, uint32_t lane, uint32_t* err)
 {
     for (uint32_t j = lane; j < uq.n; j += 64) {
@@ -282,15 +287,14 @@ __device__ __forceinline__ void drain(UnionQueue& uq, uint32_t* P, uint32_t lane
     uq.n = 0;
 }
 
-__device__ __forceinline__ void enqueue(UnionQueue& uq, bool pred, uint32_t a, uint32_t b, uint32_t* P,
-                                        uint32_t lane, uint32_t* err)
+// Queue the unions of the lanes where pred holds (at most 64; the caller keeps
+// at least 64 slots free).
+__device__ __forceinline__ void enqueue(UnionQueue& uq, bool pred, uint32_t a, uint32_t b)
 {
     const uint64_t m = ballot(pred);
     if (!m) return;
-    const uint32_t cnt = popc64(m);
-    if (uq.n + cnt > QCAP) drain(uq, P, lane, err);
     if (pred) lds_st(&uq.q[uq.n + lanes_below(m)], a | (b << 16));
-    uq.n += cnt;
+    uq.n = __builtin_amdgcn_readfirstlane(uq.n + popc64(m));
 }
 
 // Provisional labels of one tile row, Hoshen-Kopelman style.  hx: +x bonds
@@ -301,8 +305,7 @@ __device__ __forceinline__ void enqueue(UnionQueue& uq, bool pred, uint32_t a, u
 // per run carries the choice to all its sites.  Any further +y bond into the
 // run from a differently labelled site queues a union.
 __device__ __forceinline__ uint32_t row_labels(uint32_t* P, uint32_t* rl, UnionQueue& uq, uint32_t r, uint32_t x,
-                                               uint64_t validm, uint64_t hx, uint64_t V, uint64_t hprev, uint32_t lp,
-                                               uint32_t* err)
+                                               uint64_t validm, uint64_t hx, uint64_t V, uint64_t hprev, uint32_t lp)
 {
     const uint64_t C = hx << 1;                 // bit x: bond (x-1) -> x
     const uint64_t S = ~C & validm;             // first sites of runs
@@ -315,7 +318,7 @@ __device__ __forceinline__ uint32_t row_labels(uint32_t* P, uint32_t* rl, UnionQ
     if (lane_in(S) && lab == fresh) lds_st(&P[fresh], fresh);
     // bonds x-1 and x from the same run above into the same run here add nothing
     const uint64_t R = V & (V << 1) & C & (hprev << 1);
-    enqueue(uq, lane_in(V & ~R) && lp != lab, lp, lab, P, x, err);
+    enqueue(uq, lane_in(V & ~R) && lp != lab, lp, lab);
     return lab;
 }
 
@@ -346,6 +349,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     __shared__ uint32_t RL[4][64];     // per wave: the label of every run of a row
     __shared__ uint32_t seam[4][64];   // labels of each strip's last row
     __shared__ uint32_t UQ[4][QCAP];   // per wave: pending unions
+    __shared__ uint16_t prov[TY * TX]; // provisional label of every site
     __shared__ uint32_t hist[256];
     __shared__ uint32_t tot[2];
 
@@ -353,7 +357,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     uint32_t tile;
     if (!pick(descs, map, blockIdx.x, true, d, tile)) return;
     const TileGeom g = tile_geom(d, tile, TY);
-    const uint32_t t = *d.counter + k;
+    const uint32_t t = *glb(d.counter) + k;
     const bool meas = d.cap != 0;
     const bool meas_prev = meas && (flags & 1u);
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
@@ -369,22 +373,18 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     const uint64_t validm = (w == 64) ? ~0ull : ((1ull << w) - 1ull);
     const uint64_t cross = 1ull << (w - 1);   // the +x bond of column w-1 leaves the tile
     const uint32_t r0 = wave * RPW, r1 = min(h, r0 + RPW);
-    const bool on = d.thr_nz != 0;
+    const uint64_t onm = d.thr_nz ? ~0ull : 0ull;   // K = 0: no bond at all
     const bool even_L = (L & 1u) == 0;
+    const bool q2 = d.q == 2;
     uint32_t* rl = RL[wave];
     UnionQueue uq{UQ[wave], 0u};
-    uint32_t n_unsat = 0, n_active = 0;
-    uint32_t prov[RPW];
+    uint32_t n_unsat = 0, n_active = 0, n_ones = 0;
     uint32_t lp = 0;
     uint64_t hprev = 0, vprev = 0;
 
-#pragma unroll
-    for (uint32_t i = 0; i < RPW; i += 2) {
-        const uint32_t r = r0 + i;
-        prov[i] = 0;
-        prov[i + 1] = 0;
-        if (r >= r1) continue;
+    for (uint32_t r = r0; r < r1; r += 2) {
         const bool two = r + 1 < r1;
+        if (uq.n > QCAP - 128) drain(uq, P, lane, d.err);
         const uint8_t* row = sp + r * SPW;
         const uint32_t s0 = row[x], s0r = row[x + 1];
         const uint32_t s1 = row[SPW + x], s1r = row[SPW + x + 1];
@@ -411,13 +411,16 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
             wx1 = (gb & 1u) ? qb.z : qb.x;
             wy1 = (gb & 1u) ? qb.w : qb.y;
         }
-        const bool ex0 = s0 == s0r, ey0 = s0 == s1, ex1 = s1 == s1r, ey1 = s1 == s2;
-        const uint64_t BX0 = ballot(vx && ex0 && on && wx0 <= d.thr_m1);
-        const uint64_t BY0 = ballot(vx && ey0 && on && wy0 <= d.thr_m1);
-        uint64_t BX1 = 0, BY1 = 0;
+        // equal-spin masks and draw masks as wave ballots; a bond needs both
+        const uint64_t EX0 = ballot(s0 == s0r) & validm, EY0 = ballot(s0 == s1) & validm;
+        const uint64_t BX0 = EX0 & ballot(wx0 <= d.thr_m1) & onm;
+        const uint64_t BY0 = EY0 & ballot(wy0 <= d.thr_m1) & onm;
+        uint64_t EX1 = 0, EY1 = 0, BX1 = 0, BY1 = 0;
         if (two) {
-            BX1 = ballot(vx && ex1 && on && wx1 <= d.thr_m1);
-            BY1 = ballot(vx && ey1 && on && wy1 <= d.thr_m1);
+            EX1 = ballot(s1 == s1r) & validm;
+            EY1 = ballot(s1 == s2) & validm;
+            BX1 = EX1 & ballot(wx1 <= d.thr_m1) & onm;
+            BY1 = EY1 & ballot(wy1 <= d.thr_m1) & onm;
         }
         if (lane == 0) {
             rb[r][0] = BX0;
@@ -429,15 +432,15 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         }
 
         const uint64_t hx0 = BX0 & ~cross;
-        const uint32_t lab0 = row_labels(P, rl, uq, r, x, validm, hx0, vprev, hprev, lp, d.err);
-        prov[i] = lab0;
+        const uint32_t lab0 = row_labels(P, rl, uq, r, x, validm, hx0, vprev, hprev, lp);
+        prov[r * TX + x] = (uint16_t)lab0;
         lp = lab0;
         hprev = hx0;
         vprev = BY0;
         if (two) {
             const uint64_t hx1 = BX1 & ~cross;
-            const uint32_t lab1 = row_labels(P, rl, uq, r + 1, x, validm, hx1, vprev, hprev, lp, d.err);
-            prov[i + 1] = lab1;
+            const uint32_t lab1 = row_labels(P, rl, uq, r + 1, x, validm, hx1, vprev, hprev, lp);
+            prov[(r + 1) * TX + x] = (uint16_t)lab1;
             lp = lab1;
             hprev = hx1;
             vprev = BY1;
@@ -446,11 +449,13 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         if (meas) {
             n_active += popc64(BX0) + popc64(BY0) + popc64(BX1) + popc64(BY1);
             if (meas_prev) {
-                n_unsat += popc64(ballot(vx && !ex0)) + popc64(ballot(vx && !ey0));
-                count_states(hist, d.q, lane, vx, s0);
+                n_unsat += popc64(validm & ~EX0) + popc64(validm & ~EY0);
+                if (q2) n_ones += popc64(ballot(s0 != 0u) & validm);
+                else count_states(hist, d.q, lane, vx, s0);
                 if (two) {
-                    n_unsat += popc64(ballot(vx && !ex1)) + popc64(ballot(vx && !ey1));
-                    count_states(hist, d.q, lane, vx, s1);
+                    n_unsat += popc64(validm & ~EX1) + popc64(validm & ~EY1);
+                    if (q2) n_ones += popc64(ballot(s1 != 0u) & validm);
+                    else count_states(hist, d.q, lane, vx, s1);
                 }
             }
         }
@@ -459,6 +464,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     if (meas && lane == 0) {
         atomicAdd(&tot[0], n_unsat);
         atomicAdd(&tot[1], n_active);
+        if (q2 && n_ones) atomicAdd(&hist[1], n_ones);
     }
     __syncthreads();
 
@@ -469,13 +475,15 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         const uint64_t hu = rb[ru][0] & ~cross, hc = rb[r0][0] & ~cross;
         const uint64_t R = V & (V << 1) & (hc << 1) & (hu << 1);
         const uint32_t up = seam[wave - 1][lane];
-        enqueue(uq, lane_in(V & ~R) && up != prov[0], up, prov[0], P, lane, d.err);
+        const uint32_t first_prov = prov[r0 * TX + x];
+        if (uq.n > QCAP - 64) drain(uq, P, lane, d.err);
+        enqueue(uq, lane_in(V & ~R) && up != first_prov, up, first_prov);
     }
     drain(uq, P, lane, d.err);
 
     // Tile record: bond words (tile-major), crossing-bond masks.
-    uint32_t* rec = d.edges + (size_t)tile * edge_words(TY);
-    uint64_t* bw = d.bonds + (size_t)tile * 2 * TY;
+    gptr<uint32_t> rec = glb(d.edges) + (size_t)tile * edge_words(TY);
+    gptr<uint64_t> bw = glb(d.bonds) + (size_t)tile * 2 * TY;
     for (uint32_t j = tid; j < 2 * TY; j += 256) {
         const uint32_t r = j % TY;
         if (r < h) bw[j] = rb[r][j / TY];
@@ -502,19 +510,24 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     }
     __syncthreads();
 
-    // Final tile-local labels as global site indices.
-#pragma unroll
-    for (uint32_t i = 0; i < RPW; ++i) {
-        const uint32_t r = r0 + i;
-        if (r >= r1) continue;
+    // Final tile-local labels as global site indices.  Lane i collects the
+    // labels of the left and right columns in strip row i.
+    uint32_t colL = 0, colR = 0;
+    for (uint32_t r = r0; r < r1; ++r) {
+        const uint32_t i = r - r0;
         // provisional labels exist only for sites inside the tile
-        const uint32_t la = vx ? lds_find(P, prov[i], d.err) : 0u;
+        const uint32_t la = vx ? lds_find(P, prov[r * TX + x], d.err) : 0u;
         const uint32_t ga = (uint32_t)((size_t)(y0 + la / TX) * L + x0 + la % TX);
-        if (vx) d.lab[(size_t)(y0 + r) * L + x0 + x] = ga;
-        if (vx && x == w - 1) rec[8 + r] = ga;
-        if (x == 0) rec[8 + TY + r] = ga;
-        if (vx && r == h - 1) rec[8 + 2 * TY + x] = ga;
-        if (vx && r == 0) rec[8 + 2 * TY + TX + x] = ga;
+        if (vx) glb(d.lab)[(size_t)(y0 + r) * L + x0 + x] = ga;
+        const uint32_t gl = __builtin_amdgcn_readlane(ga, 0), gr = __builtin_amdgcn_readlane(ga, w - 1);
+        colL = (lane == i) ? gl : colL;
+        colR = (lane == i) ? gr : colR;
+        if (r == h - 1 && vx) rec[8 + 2 * TY + x] = ga;
+        if (r == 0 && vx) rec[8 + 2 * TY + TX + x] = ga;
+    }
+    if (r0 < r1 && lane < r1 - r0) {
+        rec[8 + r0 + lane] = colR;
+        rec[8 + TY + r0 + lane] = colL;
     }
 
     if (meas) {
@@ -545,9 +558,9 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
     const uint64_t N = (uint64_t)d.L * d.L;
     const uint32_t t_right = g.ty * d.ntx + ((g.tx + 1 == d.ntx) ? 0u : g.tx + 1);
     const uint32_t t_below = ((g.ty + 1 == d.nty) ? 0u : g.ty + 1) * d.ntx + g.tx;
-    const uint32_t* rec = d.edges + (size_t)tile * EW;
-    const uint32_t* recR = d.edges + (size_t)t_right * EW;
-    const uint32_t* recB = d.edges + (size_t)t_below * EW;
+    const gptr<uint32_t> rec = glb(d.edges) + (size_t)tile * EW;
+    const gptr<uint32_t> recR = glb(d.edges) + (size_t)t_right * EW;
+    const gptr<uint32_t> recB = glb(d.edges) + (size_t)t_below * EW;
 
     // Right edge: row r joins (w-1, r) here with (0, r) of the right neighbour.
     uint32_t pa = INVALID, pb = INVALID;
@@ -567,7 +580,7 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
         pa = __shfl(a, 63);
         pb = __shfl(b, 63);
         // consecutive crossing bonds between the same two clusters: join once
-        if (bit && !(ua == a && ub == b)) g_unite(d.lab, N, a, b, d.err);
+        if (bit && !(ua == a && ub == b)) g_unite(glb(d.lab), N, a, b, d.err);
     }
     // Bottom edge: column x joins (x, h-1) here with (x, 0) of the tile below.
     {
@@ -583,7 +596,7 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
             ua = INVALID;
             ub = INVALID;
         }
-        if (bit && !(ua == a && ub == b)) g_unite(d.lab, N, a, b, d.err);
+        if (bit && !(ua == a && ub == b)) g_unite(glb(d.lab), N, a, b, d.err);
     }
 }
 
@@ -592,72 +605,60 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
 // cluster.  Inside the tile the labels form a forest whose terminals are the
 // sites that are global roots or whose parent lies outside the tile; only the
 // terminals search the global forest (compressing the paths they walk) and
-// draw a state, in compacted lanes.  Thread t owns the sites of column
-// t mod 64 in rows t/64, t/64 + 4, ...; their labels are all loaded first.
+// draw a state, in compacted lanes.  Wave w owns rows w, w+4, w+8, ... (lane =
+// column); its labels are all loaded first, and its terminals go to a list of
+// its own.
 template <int TY>
 __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkItem* map, uint32_t k)
 {
-    constexpr uint32_t PER = TY / 4;   // sites per thread
+    constexpr uint32_t PER = TY / 4;   // rows per wave
     __shared__ uint32_t E[TY * TX];
-    __shared__ uint16_t list[TY * TX];
-    __shared__ uint32_t nlist;
+    __shared__ uint16_t list[4][PER * TX];
 
     LatDesc d;
     uint32_t tile;
     if (!pick(descs, map, blockIdx.x, true, d, tile)) return;
     const TileGeom g = tile_geom(d, tile, TY);
-    const uint32_t t = *d.counter + k;
-    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t t = *glb(d.counter) + k;
+    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     const uint32_t L = d.L, w = g.w, h = g.h, x0 = g.x0, y0 = g.y0;
-    const uint32_t col = lane, rr = tid >> 6;
+    const uint32_t col = lane;
     const bool vcol = col < w;
+    uint16_t* my_list = list[wave];
 
-    if (tid == 0) nlist = 0;
     uint32_t v[PER];
 #pragma unroll
     for (uint32_t j = 0; j < PER; ++j) {
-        const uint32_t r = rr + 4 * j;
-        v[j] = (vcol && r < h) ? d.lab[(size_t)(y0 + r) * L + x0 + col] : 0u;
+        const uint32_t r = wave + 4 * j;
+        v[j] = (vcol && r < h) ? glb(d.lab)[(size_t)(y0 + r) * L + x0 + col] : 0u;
     }
-    __syncthreads();
 
+    uint32_t nterm = 0;   // wave-uniform
 #pragma unroll
     for (uint32_t j = 0; j < PER; ++j) {
-        const uint32_t r = rr + 4 * j;
-        const bool valid = vcol && r < h;
+        const uint32_t r = wave + 4 * j;
+        if (r >= h) continue;
         const uint32_t li = r * TX + col;
-        bool term = false;
-        if (valid) {
-            const uint32_t gi = (uint32_t)((size_t)(y0 + r) * L + x0 + col);
-            term = true;
-            if (v[j] != gi) {
-                const uint32_t vy = div_L(d, v[j]);
-                const uint32_t dy = vy - y0, dx = (v[j] - vy * L) - x0;
-                if (dy < h && dx < w) {
-                    E[li] = dy * TX + dx;
-                    term = false;
-                }
-            }
-            if (term) E[li] = v[j];
-        }
+        const uint32_t gi = (uint32_t)((size_t)(y0 + r) * L + x0) + col;
+        const uint32_t vv = v[j];
+        // tile coordinates of the label (meaningless, and rejected, outside the tile)
+        const uint32_t vy = div_L(d, vv);
+        const uint32_t dy = vy - y0, dx = (vv - vy * L) - x0;
+        const bool term = vcol && (vv == gi || dy >= h || dx >= w);
+        if (vcol) E[li] = term ? vv : dy * TX + dx;
         const uint64_t m = ballot(term);
-        if (m) {
-            uint32_t at = 0;
-            if (lane == 0) at = atomicAdd(&nlist, popc64(m));
-            at = __shfl(at, 0);
-            if (term) list[at + lanes_below(m)] = (uint16_t)li;
-        }
+        if (term) my_list[nterm + lanes_below(m)] = (uint16_t)li;
+        nterm = __builtin_amdgcn_readfirstlane(nterm + popc64(m));
     }
-    __syncthreads();
 
-    const uint32_t n = nlist;
-    for (uint32_t j = tid; j < n; j += 256) {
-        const uint32_t li = list[j];
+    // a wave resolves the terminals it found (all its own entries of E)
+    for (uint32_t j = lane; j < nterm; j += 64) {
+        const uint32_t li = my_list[j];
         const uint32_t vv = E[li];
         const uint32_t gi = (uint32_t)((size_t)(y0 + li / TX) * L + x0 + li % TX);
         uint32_t root = vv;
         if (vv != gi) {
-            if (vv < gi) root = g_root_compress(d.lab, vv, d.err);
+            if (vv < gi) root = g_root_compress(glb(d.lab), vv, d.err);
             else flag_error(d.err);
         }
         E[li] = TERM | cluster_state(d, root, t);
@@ -666,18 +667,26 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
 
 #pragma unroll
     for (uint32_t j = 0; j < PER; ++j) {
-        const uint32_t r = rr + 4 * j;
-        if (!(vcol && r < h)) continue;
-        uint32_t e = E[r * TX + col];
-        // in-tile pointers strictly decrease, so this chase ends
-        for (uint32_t it = 0; it < LDS_CAP && !(e & TERM); ++it) e = E[e];
-        if (!(e & TERM)) flag_error(d.err);
-        d.s[(size_t)(y0 + r) * L + x0 + col] = (uint8_t)e;
+        const uint32_t r = wave + 4 * j;
+        if (r >= h) continue;
+        uint32_t e = 0;
+        if (vcol) {
+            e = E[r * TX + col];
+            // a site points at its tile-local root, which is mostly a terminal
+            const uint32_t e2 = E[e & (TY * TX - 1)];
+            e = (e & TERM) ? e : e2;
+        }
+        if (ballot(vcol && !(e & TERM))) {
+            // longer in-tile chains (strictly decreasing pointers, so they end)
+            for (uint32_t it = 0; it < LDS_CAP && vcol && !(e & TERM); ++it) e = E[e];
+            if (vcol && !(e & TERM)) flag_error(d.err);
+        }
+        if (vcol) glb(d.s)[(size_t)(y0 + r) * L + x0 + col] = (uint8_t)e;
     }
 
     // The ring record of the next sweep starts from zero.
     if (d.cap && tile == 0) {
-        int64_t* rec = d.ring + (size_t)((t + 1) % d.cap) * NCOPY * (d.q + 1);
+        gptr<int64_t> rec = glb(d.ring) + (size_t)((t + 1) % d.cap) * NCOPY * (d.q + 1);
         for (uint32_t i = tid; i < NCOPY * (d.q + 1); i += 256) rec[i] = 0;
     }
 }
@@ -703,7 +712,7 @@ __global__ __launch_bounds__(256) void k_measure(const LatDesc* descs, const Wor
         k = nl - 1;
     }
     const TileGeom g = tile_geom(d, tile, TY);
-    const uint32_t t = *d.counter + k;
+    const uint32_t t = *glb(d.counter) + k;
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     const uint32_t w = g.w, h = g.h;
     hist[tid] = 0;
@@ -733,7 +742,7 @@ __global__ __launch_bounds__(256) void k_init(const LatDesc* descs, uint32_t lat
     const LatDesc d = descs[lat];
     const size_t N = (size_t)d.L * d.L;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
-        d.s[i] = random_start
+        glb(d.s)[i] = random_start
                      ? (uint8_t)state_of_draw(philox4x32_10((uint32_t)i, 0u, 0u, 2u, d.key0, d.key1).x, d.q)
                      : (uint8_t)0;
     }
@@ -745,8 +754,8 @@ __global__ __launch_bounds__(256) void k_resolve(const LatDesc* descs, uint32_t 
     const LatDesc d = descs[lat];
     const size_t N = (size_t)d.L * d.L;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t v = d.lab[i];
-        if (v <= i) d.lab[i] = g_root(d.lab, v, d.err);
+        const uint32_t v = glb(d.lab)[i];
+        if (v <= i) glb(d.lab)[i] = g_root(glb(d.lab), v, d.err);
         else flag_error(d.err);
     }
 }
@@ -757,7 +766,7 @@ __global__ void k_bump(const LatDesc* descs, uint32_t count, const uint32_t* n_e
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) {
         const uint32_t add = n_each ? n_each[i] : n;
-        if (add) *descs[i].counter += add;
+        if (add) *glb(descs[i].counter) += add;
     }
 }
 
