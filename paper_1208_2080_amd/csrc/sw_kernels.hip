@@ -84,7 +84,7 @@ __device__ __forceinline__ uint32_t swap_pair(uint32_t v)
 }
 
 // ------------------------------------------------------- LDS union-find
-// P holds, for every provisional label of the tile, a label that is never
+// P holds, for every site of the tile (tile-local index), a label that is never
 // larger than itself; roots point at themselves.  Finds halve paths with plain
 // stores (a stored value is always an ancestor, so races are benign); unions
 // hook the larger root under the smaller one with atomicMin and retry from the
@@ -303,7 +303,9 @@ __device__ __forceinline__ void enqueue(UnionQueue& uq, bool pred, uint32_t a, u
 // label: the label above one of its +y bonds, or, with none, its first site
 // (a new root).  The runs are numbered by their first sites, and one LDS slot
 // per run carries the choice to all its sites.  Any further +y bond into the
-// run from a differently labelled site queues a union.
+// run from a differently labelled site queues a union.  Every site's own
+// union-find entry points at its label (itself for a new root), so the forest
+// spans all sites and no separate array of provisional labels is kept.
 __device__ __forceinline__ uint32_t row_labels(uint32_t* P, uint32_t* rl, UnionQueue& uq, uint32_t r, uint32_t x,
                                                uint64_t validm, uint64_t hx, uint64_t V, uint64_t hprev, uint32_t lp)
 {
@@ -315,7 +317,7 @@ __device__ __forceinline__ uint32_t row_labels(uint32_t* P, uint32_t* rl, UnionQ
     if (lane_in(S)) lds_st(&rl[ri], fresh);
     if (lane_in(V)) lds_st(&rl[ri], lp);
     const uint32_t lab = lds_ld(&rl[ri]);
-    if (lane_in(S) && lab == fresh) lds_st(&P[fresh], fresh);
+    if (lane_in(validm)) lds_st(&P[fresh], lab);
     // bonds x-1 and x from the same run above into the same run here add nothing
     const uint64_t R = V & (V << 1) & C & (hprev << 1);
     enqueue(uq, lane_in(V & ~R) && lp != lab, lp, lab);
@@ -343,13 +345,12 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
                                                    uint32_t flags)
 {
     constexpr uint32_t RPW = TY / 4;   // rows per wave (even)
-    __shared__ uint32_t P[TY * TX];    // union-find over provisional labels
+    __shared__ uint32_t P[TY * TX];    // union-find over the tile's sites
     __shared__ __align__(16) uint8_t sp[(TY + 1) * SPW];
     __shared__ uint64_t rb[TY][2];     // per row: +x bond word, +y bond word
     __shared__ uint32_t RL[4][64];     // per wave: the label of every run of a row
     __shared__ uint32_t seam[4][64];   // labels of each strip's last row
     __shared__ uint32_t UQ[4][QCAP];   // per wave: pending unions
-    __shared__ uint16_t prov[TY * TX]; // provisional label of every site
     __shared__ uint32_t hist[256];
     __shared__ uint32_t tot[2];
 
@@ -433,14 +434,12 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
 
         const uint64_t hx0 = BX0 & ~cross;
         const uint32_t lab0 = row_labels(P, rl, uq, r, x, validm, hx0, vprev, hprev, lp);
-        prov[r * TX + x] = (uint16_t)lab0;
         lp = lab0;
         hprev = hx0;
         vprev = BY0;
         if (two) {
             const uint64_t hx1 = BX1 & ~cross;
             const uint32_t lab1 = row_labels(P, rl, uq, r + 1, x, validm, hx1, vprev, hprev, lp);
-            prov[(r + 1) * TX + x] = (uint16_t)lab1;
             lp = lab1;
             hprev = hx1;
             vprev = BY1;
@@ -475,7 +474,8 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         const uint64_t hu = rb[ru][0] & ~cross, hc = rb[r0][0] & ~cross;
         const uint64_t R = V & (V << 1) & (hc << 1) & (hu << 1);
         const uint32_t up = seam[wave - 1][lane];
-        const uint32_t first_prov = prov[r0 * TX + x];
+        // the site's entry is its label or, after path halving, an ancestor of it
+        const uint32_t first_prov = lds_ld(&P[r0 * TX + x]);
         if (uq.n > QCAP - 64) drain(uq, P, lane, d.err);
         enqueue(uq, lane_in(V & ~R) && up != first_prov, up, first_prov);
     }
@@ -515,10 +515,12 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     uint32_t colL = 0, colR = 0;
     for (uint32_t r = r0; r < r1; ++r) {
         const uint32_t i = r - r0;
-        // provisional labels exist only for sites inside the tile
-        const uint32_t la = vx ? lds_find(P, prov[r * TX + x], d.err) : 0u;
-        const uint32_t ga = (uint32_t)((size_t)(y0 + la / TX) * L + x0 + la % TX);
-        if (vx) glb(d.lab)[(size_t)(y0 + r) * L + x0 + x] = ga;
+        // union-find entries exist only for sites inside the tile
+        const uint32_t la = vx ? lds_find(P, r * TX + x, d.err) : 0u;
+        // a site index fits 32 bits (N <= 2^32) and y, L fit 24 bits
+        const uint32_t ga = __umul24(y0 + la / TX, L) + x0 + la % TX;
+        const gptr<uint32_t> lrow = glb(d.lab) + (size_t)(y0 + r) * L + x0;
+        if (vx) lrow[x] = ga;
         const uint32_t gl = __builtin_amdgcn_readlane(ga, 0), gr = __builtin_amdgcn_readlane(ga, w - 1);
         colL = (lane == i) ? gl : colL;
         colR = (lane == i) ? gr : colR;
