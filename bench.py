@@ -67,8 +67,8 @@ def measured_traffic(kernel: str, workload: str, tile_rows: int):
     try:
         if vals.get("kernel_source_sha256_16") != kernel_source_digest():
             return None
-        scale = float(vals["copy_scale_bytes_per_kib"])
-        return (float(vals["fetch_kib_per_dispatch"]) + float(vals["write_kib_per_dispatch"])) * scale
+        return (float(vals["fetch_kib_per_dispatch"]) * float(vals["fetch_scale_bytes_per_kib"])
+                + float(vals["write_kib_per_dispatch"]) * float(vals["write_scale_bytes_per_kib"]))
     except (KeyError, ValueError):
         return None
 

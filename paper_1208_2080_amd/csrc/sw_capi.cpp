@@ -108,7 +108,7 @@ Carve carve(const Geometry& g)
     c.lab = take(g.N * 4);
     c.bonds = take((size_t)g.ntiles * 2 * g.ty * 8);
     c.edges = take((size_t)g.ntiles * edge_words(g.ty) * 4);
-    c.ring = take((size_t)ring_slots(g) * NCOPY * (g.q + 1) * 8);
+    c.ring = take((size_t)ring_slots(g) * NCOPY * ring_stride(g.q) * 8);
     c.total = off;
     return c;
 }
@@ -195,7 +195,7 @@ int check_device_error(const LatDesc& d, hipStream_t s)
 int read_ring(const LatDesc& d, size_t N, hipStream_t s, uint32_t first, uint32_t n, int64_t* out)
 {
     if (n == 0) return SW_OK;
-    const size_t R = d.q + 1, rec = (size_t)NCOPY * R;
+    const size_t R = ring_stride(d.q), rec = (size_t)NCOPY * R;
     std::vector<int64_t> buf((size_t)n * rec);
     const uint32_t slot0 = first % d.cap;
     const uint32_t n1 = std::min<uint32_t>(n, d.cap - slot0);
@@ -288,7 +288,7 @@ int sw_init(const sw_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
     auto run = [&]() -> int {
         HIP_TRY(hipMemsetAsync(h->base + c.state, 0, sizeof(DevState), h->stream));
         HIP_TRY(hipMemcpyAsync(h->d_desc, &h->desc, sizeof(LatDesc), hipMemcpyHostToDevice, h->stream));
-        if (g.cap) HIP_TRY(hipMemsetAsync(h->base + c.ring, 0, (size_t)ring_slots(g) * NCOPY * (g.q + 1) * 8, h->stream));
+        if (g.cap) HIP_TRY(hipMemsetAsync(h->base + c.ring, 0, (size_t)ring_slots(g) * NCOPY * ring_stride(g.q) * 8, h->stream));
         if (p->init) HIP_TRY(launch_init(h->d_desc, 0, g.N, 1u, h->stream));
         else HIP_TRY(hipMemsetAsync(h->desc.s, 0, g.N, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -395,7 +395,7 @@ int sw_load_spins(sw_lattice* h, const uint8_t* host_in, uint32_t sweep)
     HIP_TRY(hipMemcpyAsync(h->desc.s, host_in, h->g.N, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(h->desc.counter, &sweep, sizeof sweep, hipMemcpyHostToDevice, h->stream));
     if (h->g.cap)
-        HIP_TRY(hipMemsetAsync(h->desc.ring, 0, (size_t)ring_slots(h->g) * NCOPY * (h->g.q + 1) * 8, h->stream));
+        HIP_TRY(hipMemsetAsync(h->desc.ring, 0, (size_t)ring_slots(h->g) * NCOPY * ring_stride(h->g.q) * 8, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->done = sweep;
     h->first_obs = sweep;
@@ -631,7 +631,7 @@ int sw_batch_init(const sw_params* params, uint32_t n, void* dev_ws, size_t ws_b
             HIP_TRY(hipMemsetAsync(base + b->c[r].state, 0, sizeof(DevState), b->stream));
             if (b->g[r].cap)
                 HIP_TRY(hipMemsetAsync(base + b->c[r].ring, 0,
-                                       (size_t)ring_slots(b->g[r]) * NCOPY * (b->g[r].q + 1) * 8, b->stream));
+                                       (size_t)ring_slots(b->g[r]) * NCOPY * ring_stride(b->g[r].q) * 8, b->stream));
             if (params[r].init) HIP_TRY(launch_init(b->d_descs, r, b->g[r].N, 1u, b->stream));
             else HIP_TRY(hipMemsetAsync(b->desc[r].s, 0, b->g[r].N, b->stream));
         }

@@ -188,21 +188,6 @@ __device__ uint32_t g_root(gptr<uint32_t> lab, uint32_t x, uint32_t* err)
     return x;
 }
 
-// Root search with path compression, once the merge is over: every node on
-// the walked path is pointed straight at the root (a benign race: any value
-// written is an ancestor of the node).
-__device__ uint32_t g_root_compress(gptr<uint32_t> lab, uint32_t x, uint32_t* err)
-{
-    const uint32_t root = g_root(lab, x, err);
-    for (uint32_t it = 0; it < FIND_CAP && x != root; ++it) {
-        const uint32_t p = lab[x];
-        if (p <= root) break;
-        lab[x] = root;
-        x = p;
-    }
-    return root;
-}
-
 // ------------------------------------------------------------ spin staging
 // Spins of a tile and its halo in LDS: rows 0..h (row h is the row below the
 // tile, periodic), columns 0..w-1 plus column w = the column right of the tile
@@ -258,7 +243,7 @@ __device__ __forceinline__ void count_states(uint32_t* hist, uint32_t q, uint32_
 // Add a workgroup's measurement into a ring record (NCOPY partial copies).
 __device__ __forceinline__ int64_t* ring_record(const LatDesc& d, uint32_t sweep, uint32_t copy)
 {
-    return d.ring + ((size_t)(sweep % d.cap) * NCOPY + copy) * (d.q + 1);   // cast at the access
+    return d.ring + ((size_t)(sweep % d.cap) * NCOPY + copy) * ring_stride(d.q);   // cast at the access
 }
 
 __device__ __forceinline__ void atomic_add_i64(int64_t* p, uint64_t v)
@@ -606,8 +591,8 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
 // Flip: every site takes the state drawn for the smallest site index of its
 // cluster.  Inside the tile the labels form a forest whose terminals are the
 // sites that are global roots or whose parent lies outside the tile; only the
-// terminals search the global forest (compressing the paths they walk) and
-// draw a state, in compacted lanes.  Wave w owns rows w, w+4, w+8, ... (lane =
+// terminals search the global forest (halving the paths they walk) and draw a
+// state, in compacted lanes.  Wave w owns rows w, w+4, w+8, ... (lane =
 // column); its labels are all loaded first, and its terminals go to a list of
 // its own.
 template <int TY>
@@ -660,7 +645,7 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
         const uint32_t gi = (uint32_t)((size_t)(y0 + li / TX) * L + x0 + li % TX);
         uint32_t root = vv;
         if (vv != gi) {
-            if (vv < gi) root = g_root_compress(glb(d.lab), vv, d.err);
+            if (vv < gi) root = g_find(glb(d.lab), vv, d.err);
             else flag_error(d.err);
         }
         E[li] = TERM | cluster_state(d, root, t);
@@ -688,8 +673,9 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
 
     // The ring record of the next sweep starts from zero.
     if (d.cap && tile == 0) {
-        gptr<int64_t> rec = glb(d.ring) + (size_t)((t + 1) % d.cap) * NCOPY * (d.q + 1);
-        for (uint32_t i = tid; i < NCOPY * (d.q + 1); i += 256) rec[i] = 0;
+        const uint32_t words = NCOPY * ring_stride(d.q);
+        gptr<int64_t> rec = glb(d.ring) + (size_t)((t + 1) % d.cap) * words;
+        for (uint32_t i = tid; i < words; i += 256) rec[i] = 0;
     }
 }
 

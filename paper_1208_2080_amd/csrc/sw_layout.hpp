@@ -8,9 +8,10 @@
 //   bonds   uint64 [tiles][2][TY]  tile-major bond words: tile t, plane p (0: +x,
 //                             1: +y), row r; bit x = bond of site (x0 + x, y0 + r)
 //   edges   uint32 [tiles][EDGE_WORDS(TY)]  per-tile boundary record (below)
-//   ring    int64  [slots][NCOPY][q+1]  per-sweep sums: n_unsat, n_active,
-//                             n_1..n_{q-1} (n_0 = N - the rest), NCOPY partial
-//                             copies to spread atomic traffic
+//   ring    int64  [slots][NCOPY][ring_stride(q)]  per-sweep sums: n_unsat,
+//                             n_active, n_1..n_{q-1} (n_0 = N - the rest);
+//                             NCOPY partial copies, each on cache lines of its
+//                             own, spread the workgroups' atomics
 //   state   DevState          sweep counter and error flag
 // Tiles are TX = 64 columns by TY rows (TY = 32, 64 or 128), numbered row-major.
 #pragma once
@@ -20,7 +21,7 @@
 namespace swmi {
 
 constexpr uint32_t TX = 64;           // tile width: one wave, one column per lane
-constexpr uint32_t NCOPY = 16;        // partial copies of each ring record
+constexpr uint32_t NCOPY = 64;        // partial copies of each ring record
 constexpr uint32_t TERM = 0x80000000u;
 constexpr uint32_t CAP_STEPS = 1u << 26;  // safety cap on any pointer-chasing loop
 constexpr uint32_t INVALID = 0xFFFFFFFFu;
@@ -34,6 +35,10 @@ constexpr uint32_t INVALID = 0xFFFFFFFFu;
 //   [8+2TY, +TX)      labels of the bottom row
 //   [8+2TY+TX, +TX)   labels of the top row
 __host__ __device__ constexpr uint32_t edge_words(uint32_t ty) { return 8u + 2u * ty + 2u * TX; }
+
+// int64 words between partial copies of a ring record: the q + 1 sums rounded
+// up to whole 256-byte blocks, so no two copies share a cache line.
+__host__ __device__ constexpr uint32_t ring_stride(uint32_t q) { return (q + 1u + 31u) & ~31u; }
 
 struct DevState {
     uint32_t err;          // nonzero: a safety cap tripped
