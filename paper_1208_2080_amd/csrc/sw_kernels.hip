@@ -71,6 +71,10 @@ __device__ __forceinline__ void flag_error(uint32_t* err)
 // Lane l's bit of a wave-uniform mask, as a lane predicate.
 __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
+// Index of this wave in its workgroup as a wave-uniform (scalar) value, for
+// kernels where work selected by it (descriptor loads) should stay scalar.
+__device__ __forceinline__ uint32_t wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // Number of set bits of a wave-uniform mask below this lane.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 {
@@ -85,10 +89,11 @@ __device__ __forceinline__ uint32_t swap_pair(uint32_t v)
 
 // ------------------------------------------------------- LDS union-find
 // P holds, for every site of the tile (tile-local index), a label that is never
-// larger than itself; roots point at themselves.  Finds halve paths with plain
-// stores (a stored value is always an ancestor, so races are benign); unions
-// hook the larger root under the smaller one with atomicMin and retry from the
-// old value when the hooked node was no longer a root.
+// larger than itself; roots point at themselves.  Entries only ever decrease
+// (unions hook the larger root under the smaller one with atomicMin; finds
+// point nodes at their grandparents), so every walk that steps only to
+// smaller indices ends.  A walk that stops at a node pointing to a larger
+// index has met a corrupted forest and sets `bad`, which the kernel reports.
 __device__ __forceinline__ uint32_t lds_ld(uint32_t* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -98,37 +103,48 @@ __device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-__device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x, uint32_t* err)
+// Root of x while unions may still run, with path splitting: every visited
+// node is pointed at its grandparent (a stored value is always an ancestor,
+// so races with other finds and hooks are benign).
+__device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x, bool& bad)
 {
-    for (uint32_t it = 0; it < LDS_CAP; ++it) {
-        const uint32_t p = lds_ld(&P[x]);
-        if (p == x) return x;
+    uint32_t p = lds_ld(&P[x]);
+    while (p < x) {
         const uint32_t gp = lds_ld(&P[p]);
-        if (p > x || gp > p) break;
-        if (gp == p) return p;
         lds_st(&P[x], gp);
-        x = gp;
+        x = p;
+        p = gp;
     }
-    flag_error(err);
+    bad |= p != x;
     return x;
 }
 
-__device__ void lds_union(uint32_t* P, uint32_t a, uint32_t b, uint32_t* err)
+// Root of x once the forest no longer changes (no writes).
+__device__ __forceinline__ uint32_t lds_root(const uint32_t* P, uint32_t x, bool& bad)
+{
+    uint32_t p = P[x];
+    while (p < x) {
+        x = p;
+        p = P[x];
+    }
+    bad |= p != x;
+    return x;
+}
+
+__device__ void lds_union(uint32_t* P, uint32_t a, uint32_t b, bool& bad)
 {
     for (uint32_t it = 0; it < LDS_CAP; ++it) {
-        a = lds_find(P, a, err);
-        b = lds_find(P, b, err);
+        a = lds_find(P, a, bad);
+        b = lds_find(P, b, bad);
         if (a == b) return;
-        if (a < b) {
-            const uint32_t t = a;
-            a = b;
-            b = t;
-        }
-        const uint32_t old = __hip_atomic_fetch_min(&P[a], b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (old == a) return;
+        const uint32_t hi = max(a, b), lo = min(a, b);
+        const uint32_t old = __hip_atomic_fetch_min(&P[hi], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (old == hi) return;
+        // hi was hooked meanwhile: join its new parent with lo instead
         a = old;
+        b = lo;
     }
-    flag_error(err);
+    bad = true;
 }
 
 // ---------------------------------------------------- global union-find
@@ -263,11 +279,11 @@ struct UnionQueue {
 };
 
 // Run the queued unions, one per lane.
-__device__ __forceinline__ void drain(UnionQueue& uq, uint32_t* P, uint32_t lane, uint32_t* err)
+__device__ __forceinline__ void drain(UnionQueue& uq, uint32_t* P, uint32_t lane, bool& bad)
 {
     for (uint32_t j = lane; j < uq.n; j += 64) {
         const uint32_t e = lds_ld(&uq.q[j]);
-        lds_union(P, e & 0xFFFFu, e >> 16, err);
+        lds_union(P, e & 0xFFFFu, e >> 16, bad);
     }
     uq.n = 0;
 }
@@ -366,11 +382,12 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     UnionQueue uq{UQ[wave], 0u};
     uint32_t n_unsat = 0, n_active = 0, n_ones = 0;
     uint32_t lp = 0;
+    bool bad = false;   // this lane met a corrupted forest
     uint64_t hprev = 0, vprev = 0;
 
     for (uint32_t r = r0; r < r1; r += 2) {
         const bool two = r + 1 < r1;
-        if (uq.n > QCAP - 128) drain(uq, P, lane, d.err);
+        if (uq.n > QCAP - 128) drain(uq, P, lane, bad);
         const uint8_t* row = sp + r * SPW;
         const uint32_t s0 = row[x], s0r = row[x + 1];
         const uint32_t s1 = row[SPW + x], s1r = row[SPW + x + 1];
@@ -461,10 +478,10 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         const uint32_t up = seam[wave - 1][lane];
         // the site's entry is its label or, after path halving, an ancestor of it
         const uint32_t first_prov = lds_ld(&P[r0 * TX + x]);
-        if (uq.n > QCAP - 64) drain(uq, P, lane, d.err);
+        if (uq.n > QCAP - 64) drain(uq, P, lane, bad);
         enqueue(uq, lane_in(V & ~R) && up != first_prov, up, first_prov);
     }
-    drain(uq, P, lane, d.err);
+    drain(uq, P, lane, bad);
 
     // Tile record: bond words (tile-major), crossing-bond masks.
     gptr<uint32_t> rec = glb(d.edges) + (size_t)tile * edge_words(TY);
@@ -501,7 +518,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     for (uint32_t r = r0; r < r1; ++r) {
         const uint32_t i = r - r0;
         // union-find entries exist only for sites inside the tile
-        const uint32_t la = vx ? lds_find(P, r * TX + x, d.err) : 0u;
+        const uint32_t la = vx ? lds_root(P, r * TX + x, bad) : 0u;
         // a site index fits 32 bits (N <= 2^32) and y, L fit 24 bits
         const uint32_t ga = __umul24(y0 + la / TX, L) + x0 + la % TX;
         const gptr<uint32_t> lrow = glb(d.lab) + (size_t)(y0 + r) * L + x0;
@@ -516,6 +533,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         rec[8 + r0 + lane] = colR;
         rec[8 + TY + r0 + lane] = colL;
     }
+    if (bad) flag_error(d.err);
 
     if (meas) {
         const uint32_t copy = blockIdx.x % NCOPY;
@@ -534,7 +552,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
 template <int TY>
 __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkItem* map, uint32_t nitems)
 {
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t wave = wave_id(), lane = threadIdx.x & 63u;
     const uint32_t idx = blockIdx.x * 4 + wave;
     if (idx >= nitems) return;
     LatDesc d;
