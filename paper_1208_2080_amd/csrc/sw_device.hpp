@@ -38,6 +38,41 @@ __device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_
     return {c0, c1, c2, c3};
 }
 
+// The ten round keys of a wave-uniform key, held in vector registers.  Kernels
+// short of scalar registers take the schedule from here; an identity DPP move
+// keeps the compiler from folding the values back into scalar registers.
+struct PhiloxKeys {
+    uint32_t k0[10], k1[10];
+};
+
+__device__ __forceinline__ PhiloxKeys philox_keys_v(uint32_t k0, uint32_t k1)
+{
+    PhiloxKeys ks;
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        ks.k0[round] = (uint32_t)__builtin_amdgcn_mov_dpp((int)(k0 + round * 0x9E3779B9u), 0xE4, 0xF, 0xF, false);
+        ks.k1[round] = (uint32_t)__builtin_amdgcn_mov_dpp((int)(k1 + round * 0xBB67AE85u), 0xE4, 0xF, 0xF, false);
+    }
+    return ks;
+}
+
+__device__ __forceinline__ u32x4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                               const PhiloxKeys& ks)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32((uint32_t)(p1 >> 32), c1, ks.k0[round], 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32((uint32_t)(p0 >> 32), c3, ks.k1[round], 0x96);
+        c0 = n0;
+        c1 = (uint32_t)p1;
+        c2 = n2;
+        c3 = (uint32_t)p0;
+    }
+    return {c0, c1, c2, c3};
+}
+
 // A 32-bit draw mapped onto one of q states: floor(w q / 2^32).
 __device__ __forceinline__ uint32_t state_of_draw(uint32_t w, uint32_t q) { return __umulhi(w, q); }
 

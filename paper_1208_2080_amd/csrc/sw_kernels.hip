@@ -21,12 +21,11 @@ namespace swmi {
 namespace {
 
 // Every label points at a site index no larger than its own (roots at
-// themselves), so every pointer chase strictly decreases and ends.  The loops
-// still check that invariant and carry step caps, so a corrupted forest sets
-// the error flag instead of spinning.
-constexpr uint32_t LDS_CAP = 1u << 15;     // > sites of the largest tile
-constexpr uint32_t FIND_CAP = 1u << 20;    // safety cap of global pointer chases
-constexpr uint32_t UNITE_CAP = 1u << 12;   // safety cap of union retries
+// themselves).  Every pointer walk steps only to strictly smaller indices, so
+// it ends even in a corrupted forest, and union retries carry caps; a forest
+// that breaks the invariant sets the error flag instead of spinning.
+constexpr uint32_t LDS_CAP = 1u << 15;     // cap of union retries in LDS (> sites of a tile)
+constexpr uint32_t UNITE_CAP = 1u << 12;   // cap of union retries in the global forest
 constexpr uint32_t SPW = TX + 4;           // LDS row stride of staged spins (bytes)
 
 struct TileGeom {
@@ -152,55 +151,54 @@ __device__ void lds_union(uint32_t* P, uint32_t a, uint32_t b, bool& bad)
 // earlier, still a smaller index in the same cluster, so chases still end and
 // only ever reach true ancestors or stale roots; the hook itself is a
 // device-coherent atomicMin that returns the current parent, and a hook on a
-// stale root retries from that value.  Hence the forest stays exact.
-__device__ uint32_t g_find(gptr<uint32_t> lab, uint32_t x, uint32_t* err)
+// stale root retries from that value.  Hence the forest stays exact.  As in
+// the LDS forest, walks step only to smaller indices (so they end and stay in
+// bounds) and a stop at a larger index sets `bad`.
+
+// Root of x with path splitting (every visited node is pointed at its
+// grandparent; any stored value is an ancestor, so races are benign).
+__device__ uint32_t g_find(gptr<uint32_t> lab, uint32_t x, bool& bad)
 {
-    for (uint32_t it = 0; it < FIND_CAP; ++it) {
-        const uint32_t p = lab[x];
-        if (p == x) return x;
-        if (p > x) break;
+    uint32_t p = lab[x];
+    while (p < x) {
         const uint32_t gp = lab[p];
-        if (gp == p) return p;
-        if (gp > p) break;
-        lab[x] = gp;
-        x = gp;
+        if (gp < p) lab[x] = gp;   // only a real shortcut is worth a store
+        x = p;
+        p = gp;
     }
-    flag_error(err);
+    bad |= p != x;
     return x;
 }
 
-__device__ void g_unite(gptr<uint32_t> lab, uint64_t N, uint32_t a, uint32_t b, uint32_t* err)
+__device__ void g_unite(gptr<uint32_t> lab, uint64_t N, uint32_t a, uint32_t b, bool& bad)
 {
     if (a >= N || b >= N) {
-        flag_error(err);
+        bad = true;
         return;
     }
     for (uint32_t it = 0; it < UNITE_CAP; ++it) {
-        a = g_find(lab, a, err);
-        b = g_find(lab, b, err);
+        a = g_find(lab, a, bad);
+        b = g_find(lab, b, bad);
         if (a == b) return;
-        if (a < b) {
-            const uint32_t t = a;
-            a = b;
-            b = t;
-        }
-        const uint32_t old = min_coherent(lab + a, b);
-        if (old == a) return;
+        const uint32_t hi = max(a, b), lo = min(a, b);
+        const uint32_t old = min_coherent(lab + hi, lo);
+        if (old == hi) return;
+        // hi was hooked meanwhile: join its new parent with lo instead
         a = old;
+        b = lo;
     }
-    flag_error(err);
+    bad = true;
 }
 
 // Read-only root search once the forest is final (after the merge kernel).
-__device__ uint32_t g_root(gptr<uint32_t> lab, uint32_t x, uint32_t* err)
+__device__ uint32_t g_root(gptr<uint32_t> lab, uint32_t x, bool& bad)
 {
-    for (uint32_t it = 0; it < FIND_CAP; ++it) {
-        const uint32_t p = lab[x];
-        if (p == x) return x;
-        if (p > x) break;
+    uint32_t p = lab[x];
+    while (p < x) {
         x = p;
+        p = lab[x];
     }
-    flag_error(err);
+    bad |= p != x;
     return x;
 }
 
@@ -362,7 +360,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     const uint32_t t = *glb(d.counter) + k;
     const bool meas = d.cap != 0;
     const bool meas_prev = meas && (flags & 1u);
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+    const uint32_t tid = threadIdx.x, wave = wave_id(), lane = tid & 63u;
     const uint32_t L = d.L, w = g.w, h = g.h, x0 = g.x0, y0 = g.y0;
 
     hist[tid] = 0;
@@ -382,6 +380,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     UnionQueue uq{UQ[wave], 0u};
     uint32_t n_unsat = 0, n_active = 0, n_ones = 0;
     uint32_t lp = 0;
+    const PhiloxKeys ks = philox_keys_v(d.key0, d.key1);
     bool bad = false;   // this lane met a corrupted forest
     uint64_t hprev = 0, vprev = 0;
 
@@ -398,7 +397,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         if (even_L) {
             const bool odd = x & 1u;
             const uint32_t pair = (uint32_t)(((odd ? base0 + L : base0) + (x & ~1u)) >> 1);
-            const u32x4 q4 = philox4x32_10(pair, 0u, t, 0u, d.key0, d.key1);
+            const u32x4 q4 = philox4x32_10(pair, 0u, t, 0u, ks);
             const uint32_t recv0 = swap_pair(odd ? q4.x : q4.z);
             const uint32_t recv1 = swap_pair(odd ? q4.y : q4.w);
             wx0 = odd ? recv0 : q4.x;
@@ -407,8 +406,8 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
             wy1 = odd ? q4.w : recv1;
         } else {
             const uint32_t ga = (uint32_t)(base0 + x), gb = (uint32_t)(base0 + L + x);
-            const u32x4 qa = philox4x32_10(ga >> 1, 0u, t, 0u, d.key0, d.key1);
-            const u32x4 qb = philox4x32_10(gb >> 1, 0u, t, 0u, d.key0, d.key1);
+            const u32x4 qa = philox4x32_10(ga >> 1, 0u, t, 0u, ks);
+            const u32x4 qb = philox4x32_10(gb >> 1, 0u, t, 0u, ks);
             wx0 = (ga & 1u) ? qa.z : qa.x;
             wy0 = (ga & 1u) ? qa.w : qa.y;
             wx1 = (gb & 1u) ? qb.z : qb.x;
@@ -567,6 +566,7 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
     const gptr<uint32_t> recR = glb(d.edges) + (size_t)t_right * EW;
     const gptr<uint32_t> recB = glb(d.edges) + (size_t)t_below * EW;
 
+    bool bad = false;
     // Right edge: row r joins (w-1, r) here with (0, r) of the right neighbour.
     uint32_t pa = INVALID, pb = INVALID;
     for (uint32_t j = 0; j < TY; j += 64) {
@@ -585,7 +585,7 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
         pa = __shfl(a, 63);
         pb = __shfl(b, 63);
         // consecutive crossing bonds between the same two clusters: join once
-        if (bit && !(ua == a && ub == b)) g_unite(glb(d.lab), N, a, b, d.err);
+        if (bit && !(ua == a && ub == b)) g_unite(glb(d.lab), N, a, b, bad);
     }
     // Bottom edge: column x joins (x, h-1) here with (x, 0) of the tile below.
     {
@@ -601,8 +601,9 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
             ua = INVALID;
             ub = INVALID;
         }
-        if (bit && !(ua == a && ub == b)) g_unite(glb(d.lab), N, a, b, d.err);
+        if (bit && !(ua == a && ub == b)) g_unite(glb(d.lab), N, a, b, bad);
     }
+    if (bad) flag_error(d.err);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,37 +658,41 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
     }
 
     // a wave resolves the terminals it found (all its own entries of E)
+    bool bad = false;
     for (uint32_t j = lane; j < nterm; j += 64) {
         const uint32_t li = my_list[j];
         const uint32_t vv = E[li];
         const uint32_t gi = (uint32_t)((size_t)(y0 + li / TX) * L + x0 + li % TX);
         uint32_t root = vv;
-        if (vv != gi) {
-            if (vv < gi) root = g_find(glb(d.lab), vv, d.err);
-            else flag_error(d.err);
-        }
+        if (vv < gi) root = g_find(glb(d.lab), vv, bad);
+        bad |= vv > gi;
         E[li] = TERM | cluster_state(d, root, t);
     }
     __syncthreads();
 
+    // Every site follows in-tile pointers (each to a smaller tile index, so
+    // the walk ends) to a resolved entry; the new spins are stored at the end.
+    uint32_t e[PER];
 #pragma unroll
     for (uint32_t j = 0; j < PER; ++j) {
         const uint32_t r = wave + 4 * j;
-        if (r >= h) continue;
-        uint32_t e = 0;
-        if (vcol) {
-            e = E[r * TX + col];
-            // a site points at its tile-local root, which is mostly a terminal
-            const uint32_t e2 = E[e & (TY * TX - 1)];
-            e = (e & TERM) ? e : e2;
+        e[j] = TERM;
+        if (vcol && r < h) {
+            uint32_t cur = r * TX + col, v = E[cur];
+            while (!(v & TERM) && v < cur) {
+                cur = v;
+                v = E[cur];
+            }
+            bad |= !(v & TERM);
+            e[j] = v;
         }
-        if (ballot(vcol && !(e & TERM))) {
-            // longer in-tile chains (strictly decreasing pointers, so they end)
-            for (uint32_t it = 0; it < LDS_CAP && vcol && !(e & TERM); ++it) e = E[e];
-            if (vcol && !(e & TERM)) flag_error(d.err);
-        }
-        if (vcol) glb(d.s)[(size_t)(y0 + r) * L + x0 + col] = (uint8_t)e;
     }
+#pragma unroll
+    for (uint32_t j = 0; j < PER; ++j) {
+        const uint32_t r = wave + 4 * j;
+        if (vcol && r < h) glb(d.s)[(size_t)(y0 + r) * L + x0 + col] = (uint8_t)e[j];
+    }
+    if (bad) flag_error(d.err);
 
     // The ring record of the next sweep starts from zero.
     if (d.cap && tile == 0) {
@@ -761,8 +766,9 @@ __global__ __launch_bounds__(256) void k_resolve(const LatDesc* descs, uint32_t 
     const size_t N = (size_t)d.L * d.L;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
         const uint32_t v = glb(d.lab)[i];
-        if (v <= i) glb(d.lab)[i] = g_root(glb(d.lab), v, d.err);
-        else flag_error(d.err);
+        bool bad = v > i;
+        if (!bad) glb(d.lab)[i] = g_root(glb(d.lab), v, bad);
+        if (bad) flag_error(d.err);
     }
 }
 

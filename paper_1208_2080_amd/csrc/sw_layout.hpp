@@ -23,7 +23,6 @@ namespace swmi {
 constexpr uint32_t TX = 64;           // tile width: one wave, one column per lane
 constexpr uint32_t NCOPY = 64;        // partial copies of each ring record
 constexpr uint32_t TERM = 0x80000000u;
-constexpr uint32_t CAP_STEPS = 1u << 26;  // safety cap on any pointer-chasing loop
 constexpr uint32_t INVALID = 0xFFFFFFFFu;
 
 // Boundary record of a tile with TY rows (uint32 words):
