@@ -272,8 +272,9 @@ __device__ __forceinline__ void atomic_add_i64(int64_t* p, uint64_t v)
 constexpr uint32_t QCAP = 256;   // a two-row step queues at most 128
 
 struct UnionQueue {
-    uint32_t* q;   // QCAP slots in LDS
-    uint32_t n;    // wave-uniform fill
+    uint32_t* q;       // QCAP slots in LDS
+    uint32_t* trash;   // an LDS word for lanes with nothing to store
+    uint32_t n;        // wave-uniform fill
 };
 
 // Run the queued unions, one per lane.
@@ -287,12 +288,13 @@ __device__ __forceinline__ void drain(UnionQueue& uq, uint32_t* P, uint32_t lane
 }
 
 // Queue the unions of the lanes where pred holds (at most 64; the caller keeps
-// at least 64 slots free).
+// at least 64 slots free).  The other lanes store to a scratch word instead of
+// branching around the store.
 __device__ __forceinline__ void enqueue(UnionQueue& uq, bool pred, uint32_t a, uint32_t b)
 {
     const uint64_t m = ballot(pred);
     if (!m) return;
-    if (pred) lds_st(&uq.q[uq.n + lanes_below(m)], a | (b << 16));
+    lds_st(pred ? &uq.q[uq.n + lanes_below(m)] : uq.trash, a | (b << 16));
     uq.n = __builtin_amdgcn_readfirstlane(uq.n + popc64(m));
 }
 
@@ -312,11 +314,13 @@ __device__ __forceinline__ uint32_t row_labels(uint32_t* P, uint32_t* rl, UnionQ
     const uint64_t S = ~C & validm;             // first sites of runs
     const uint32_t ri = lanes_below(S >> 1);    // number of run starts in 1..x = run index of x
     const uint32_t fresh = r * TX + x;
-    // lanes talk through the slots, so these accesses must not be folded away
-    if (lane_in(S)) lds_st(&rl[ri], fresh);
-    if (lane_in(V)) lds_st(&rl[ri], lp);
+    // lanes talk through the slots, so these accesses must not be folded away;
+    // a run's first site offers itself and every +y bond offers the label
+    // above, in one store: any offer may win (unions below cover the rest)
+    const bool vb = lane_in(V);
+    lds_st(lane_in(S | V) ? &rl[ri] : &rl[64], vb ? lp : fresh);
     const uint32_t lab = lds_ld(&rl[ri]);
-    if (lane_in(validm)) lds_st(&P[fresh], lab);
+    lds_st(&P[fresh], lab);   // columns outside the tile write entries no one reads
     // bonds x-1 and x from the same run above into the same run here add nothing
     const uint64_t R = V & (V << 1) & C & (hprev << 1);
     enqueue(uq, lane_in(V & ~R) && lp != lab, lp, lab);
@@ -347,8 +351,11 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     __shared__ uint32_t P[TY * TX];    // union-find over the tile's sites
     __shared__ __align__(16) uint8_t sp[(TY + 1) * SPW];
     __shared__ uint64_t rb[TY][2];     // per row: +x bond word, +y bond word
-    __shared__ uint32_t RL[4][64];     // per wave: the label of every run of a row
-    __shared__ uint32_t seam[4][64];   // labels of each strip's last row
+    // per wave: the label of every run of a row; once a wave has left its
+    // strip, its row holds the labels of the strip's last row (the seam)
+    __shared__ uint32_t RL[4][65];     // [64]: scratch word of lanes with nothing to store
+    __shared__ uint32_t UQT[4];        // scratch words of the union queues
+    uint32_t(*const seam)[65] = RL;
     __shared__ uint32_t UQ[4][QCAP];   // per wave: pending unions
     __shared__ uint32_t hist[256];
     __shared__ uint32_t tot[2];
@@ -377,7 +384,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     const bool even_L = (L & 1u) == 0;
     const bool q2 = d.q == 2;
     uint32_t* rl = RL[wave];
-    UnionQueue uq{UQ[wave], 0u};
+    UnionQueue uq{UQ[wave], &UQT[wave], 0u};
     uint32_t n_unsat = 0, n_active = 0, n_ones = 0;
     uint32_t lp = 0;
     const PhiloxKeys ks = philox_keys_v(d.key0, d.key1);
