@@ -639,7 +639,7 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
 {
     constexpr uint32_t PER = TY / 4;   // rows per wave
     __shared__ uint32_t E[TY * TX];
-    __shared__ uint16_t list[4][PER * TX];
+    __shared__ uint16_t list[4][PER * TX + 64];   // + a scratch slot per lane
 
     LatDesc d;
     uint32_t tile;
@@ -649,69 +649,80 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     const uint32_t L = d.L, w = g.w, h = g.h, x0 = g.x0, y0 = g.y0;
     const uint32_t col = lane;
-    const bool vcol = col < w;
     uint16_t* my_list = list[wave];
-
-    uint32_t v[PER];
-#pragma unroll
-    for (uint32_t j = 0; j < PER; ++j) {
-        const uint32_t r = wave + 4 * j;
-        v[j] = (vcol && r < h) ? glb(d.lab)[(size_t)(y0 + r) * L + x0 + col] : 0u;
-    }
-
-    uint32_t nterm = 0;   // wave-uniform
-#pragma unroll
-    for (uint32_t j = 0; j < PER; ++j) {
-        const uint32_t r = wave + 4 * j;
-        if (r >= h) continue;
-        const uint32_t li = r * TX + col;
-        const uint32_t gi = (uint32_t)((size_t)(y0 + r) * L + x0) + col;
-        const uint32_t vv = v[j];
-        // tile coordinates of the label (meaningless, and rejected, outside the tile)
-        const uint32_t vy = div_L(d, vv);
-        const uint32_t dy = vy - y0, dx = (vv - vy * L) - x0;
-        const bool term = vcol && (vv == gi || dy >= h || dx >= w);
-        if (vcol) E[li] = term ? vv : dy * TX + dx;
-        const uint64_t m = ballot(term);
-        if (term) my_list[nterm + lanes_below(m)] = (uint16_t)li;
-        nterm = __builtin_amdgcn_readfirstlane(nterm + popc64(m));
-    }
-
-    // a wave resolves the terminals it found (all its own entries of E)
+    const gptr<uint32_t> lab = glb(d.lab);
     bool bad = false;
-    for (uint32_t j = lane; j < nterm; j += 64) {
-        const uint32_t li = my_list[j];
-        const uint32_t vv = E[li];
-        const uint32_t gi = (uint32_t)((size_t)(y0 + li / TX) * L + x0 + li % TX);
-        uint32_t root = vv;
-        if (vv < gi) root = g_find(glb(d.lab), vv, bad);
-        bad |= vv > gi;
-        E[li] = TERM | cluster_state(d, root, t);
-    }
-    __syncthreads();
 
-    // Every site follows in-tile pointers (each to a smaller tile index, so
-    // the walk ends) to a resolved entry; the new spins are stored at the end.
-    uint32_t e[PER];
+    // Full tiles (the common case) need no masks for columns or rows outside.
+    auto body = [&](auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        const bool vcol = FULL || col < w;
+        uint32_t v[PER];
 #pragma unroll
-    for (uint32_t j = 0; j < PER; ++j) {
-        const uint32_t r = wave + 4 * j;
-        e[j] = TERM;
-        if (vcol && r < h) {
-            uint32_t cur = r * TX + col, v = E[cur];
-            while (!(v & TERM) && v < cur) {
-                cur = v;
-                v = E[cur];
-            }
-            bad |= !(v & TERM);
-            e[j] = v;
+        for (uint32_t j = 0; j < PER; ++j) {
+            const uint32_t r = wave + 4 * j;
+            v[j] = (vcol && (FULL || r < h)) ? lab[(size_t)(y0 + r) * L + x0 + col] : 0u;
         }
-    }
+
+        uint32_t nterm = 0;   // wave-uniform
 #pragma unroll
-    for (uint32_t j = 0; j < PER; ++j) {
-        const uint32_t r = wave + 4 * j;
-        if (vcol && r < h) glb(d.s)[(size_t)(y0 + r) * L + x0 + col] = (uint8_t)e[j];
-    }
+        for (uint32_t j = 0; j < PER; ++j) {
+            const uint32_t r = wave + 4 * j;
+            if (!FULL && r >= h) continue;
+            const uint32_t li = r * TX + col;
+            const uint32_t gi = (uint32_t)((size_t)(y0 + r) * L + x0) + col;
+            const uint32_t vv = v[j];
+            // tile coordinates of the label (meaningless, and rejected, outside the tile)
+            const uint32_t vy = div_L(d, vv);
+            const uint32_t dy = vy - y0, dx = (vv - vy * L) - x0;
+            const bool term = vcol && (vv == gi || dy >= (FULL ? TY : h) || dx >= (FULL ? TX : w));
+            if (vcol) E[li] = term ? vv : dy * TX + dx;
+            const uint64_t m = ballot(term);
+            my_list[term ? nterm + lanes_below(m) : PER * TX + lane] = (uint16_t)li;
+            nterm = __builtin_amdgcn_readfirstlane(nterm + popc64(m));
+        }
+
+        // a wave resolves the terminals it found (all its own entries of E),
+        // 64 at a time; lanes past the end work on a copy they do not store
+        for (uint32_t j0 = 0; j0 < nterm; j0 += 64) {
+            const uint32_t j = j0 + lane;
+            const bool act = j < nterm;
+            const uint32_t li = my_list[act ? j : 0];
+            const uint32_t vv = E[li];
+            const uint32_t gi = (uint32_t)((size_t)(y0 + li / TX) * L + x0 + li % TX);
+            uint32_t root = vv;
+            if (act && vv < gi) root = g_find(lab, vv, bad);
+            bad |= act && vv > gi;
+            const uint32_t st = TERM | cluster_state(d, root, t);
+            if (act) E[li] = st;
+        }
+        __syncthreads();
+
+        // Every site follows in-tile pointers (each to a smaller tile index, so
+        // the walk ends) to a resolved entry; the new spins are stored at the end.
+        uint32_t e[PER];
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j) {
+            const uint32_t r = wave + 4 * j;
+            e[j] = TERM;
+            if (vcol && (FULL || r < h)) {
+                uint32_t cur = r * TX + col, v = E[cur];
+                while (!(v & TERM) && v < cur) {
+                    cur = v;
+                    v = E[cur];
+                }
+                bad |= !(v & TERM);
+                e[j] = v;
+            }
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j) {
+            const uint32_t r = wave + 4 * j;
+            if (vcol && (FULL || r < h)) glb(d.s)[(size_t)(y0 + r) * L + x0 + col] = (uint8_t)e[j];
+        }
+    };
+    if (w == TX && h == TY) body(std::true_type{});
+    else body(std::false_type{});
     if (bad) flag_error(d.err);
 
     // The ring record of the next sweep starts from zero.
