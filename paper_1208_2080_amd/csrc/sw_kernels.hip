@@ -120,10 +120,14 @@ __device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x, bool& bad)
     return x;
 }
 
-// Root of x once the forest no longer changes (no writes).
+// Root of x once the forest no longer changes (no writes).  The first two
+// steps are taken without a branch (a root reads itself again), which covers
+// most sites; only deeper chains enter the loop.
 __device__ __forceinline__ uint32_t lds_root(const uint32_t* P, uint32_t x, bool& bad)
 {
     uint32_t p = P[x];
+    x = min(p, x);
+    p = P[x];
     while (p < x) {
         x = p;
         p = P[x];
@@ -401,11 +405,13 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         const uint32_t s1 = row[SPW + x], s1r = row[SPW + x + 1];
         const uint32_t s2 = two ? row[2 * SPW + x] : 0u;
 
-        const size_t base0 = (size_t)(y0 + r) * L + x0;
+        // Site indices in 32 bits: exact for every row of the lattice (N <= 2^32);
+        // a draw for row r+1 past the last row wraps but is never used.
+        const uint32_t base0 = (y0 + r) * L + x0;
         uint32_t wx0, wy0, wx1, wy1;
         if (even_L) {
             const bool odd = x & 1u;
-            const uint32_t pair = (uint32_t)(((odd ? base0 + L : base0) + (x & ~1u)) >> 1);
+            const uint32_t pair = ((odd ? base0 + L : base0) + (x & ~1u)) >> 1;
             const u32x4 q4 = philox4x32_10(pair, 0u, t, 0u, ks);
             const uint32_t recv0 = swap_pair(odd ? q4.x : q4.z);
             const uint32_t recv1 = swap_pair(odd ? q4.y : q4.w);
@@ -414,7 +420,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
             wx1 = odd ? q4.z : recv0;
             wy1 = odd ? q4.w : recv1;
         } else {
-            const uint32_t ga = (uint32_t)(base0 + x), gb = (uint32_t)(base0 + L + x);
+            const uint32_t ga = base0 + x, gb = base0 + L + x;
             const u32x4 qa = philox4x32_10(ga >> 1, 0u, t, 0u, ks);
             const u32x4 qb = philox4x32_10(gb >> 1, 0u, t, 0u, ks);
             wx0 = (ga & 1u) ? qa.z : qa.x;
@@ -670,11 +676,12 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
             const uint32_t r = wave + 4 * j;
             if (!FULL && r >= h) continue;
             const uint32_t li = r * TX + col;
-            const uint32_t gi = (uint32_t)((size_t)(y0 + r) * L + x0) + col;
+            // site indices fit 32 bits (N <= 2^32) and rows, L fit 24 bits
+            const uint32_t gi = __umul24(y0 + r, L) + x0 + col;
             const uint32_t vv = v[j];
             // tile coordinates of the label (meaningless, and rejected, outside the tile)
             const uint32_t vy = div_L(d, vv);
-            const uint32_t dy = vy - y0, dx = (vv - vy * L) - x0;
+            const uint32_t dy = vy - y0, dx = (vv - __umul24(vy, L)) - x0;
             const bool term = vcol && (vv == gi || dy >= (FULL ? TY : h) || dx >= (FULL ? TX : w));
             if (vcol) E[li] = term ? vv : dy * TX + dx;
             const uint64_t m = ballot(term);
@@ -689,7 +696,7 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
             const bool act = j < nterm;
             const uint32_t li = my_list[act ? j : 0];
             const uint32_t vv = E[li];
-            const uint32_t gi = (uint32_t)((size_t)(y0 + li / TX) * L + x0 + li % TX);
+            const uint32_t gi = __umul24(y0 + li / TX, L) + x0 + li % TX;
             uint32_t root = vv;
             if (act && vv < gi) root = g_find(lab, vv, bad);
             bad |= act && vv > gi;
