@@ -293,14 +293,14 @@ __device__ __forceinline__ void drain(UnionQueue& uq, uint32_t* P, uint32_t lane
     uq.n = 0;
 }
 
-// Queue the unions of the lanes where pred holds (at most 64; the caller keeps
-// at least 64 slots free).  The other lanes store to a scratch word instead of
-// branching around the store.
-__device__ __forceinline__ void enqueue(UnionQueue& uq, bool pred, uint32_t a, uint32_t b)
+// Queue the unions (a, b) of the lanes in `mask` where a != b (at most 64; the
+// caller keeps at least 64 slots free).  The other lanes store to a scratch
+// word instead of branching around the store.
+__device__ __forceinline__ void enqueue(UnionQueue& uq, uint64_t mask, uint32_t a, uint32_t b)
 {
-    const uint64_t m = ballot(pred);
+    const uint64_t m = ballot(a != b) & mask;
     if (!m) return;
-    lds_st(pred ? &uq.q[uq.n + lanes_below(m)] : uq.trash, a | (b << 16));
+    lds_st(lane_in(m) ? &uq.q[uq.n + lanes_below(m)] : uq.trash, a | (b << 16));
     uq.n = __builtin_amdgcn_readfirstlane(uq.n + popc64(m));
 }
 
@@ -329,7 +329,7 @@ __device__ __forceinline__ uint32_t row_labels(uint32_t* P, uint32_t* rl, UnionQ
     lds_st(&P[fresh], lab);   // columns outside the tile write entries no one reads
     // bonds x-1 and x from the same run above into the same run here add nothing
     const uint64_t R = V & (V << 1) & C & (hprev << 1);
-    enqueue(uq, lane_in(V & ~R) && lp != lab, lp, lab);
+    enqueue(uq, V & ~R, lp, lab);
     return lab;
 }
 
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     const uint64_t validm = (w == 64) ? ~0ull : ((1ull << w) - 1ull);
     const uint64_t cross = 1ull << (w - 1);   // the +x bond of column w-1 leaves the tile
     const uint32_t r0 = wave * RPW, r1 = min(h, r0 + RPW);
-    const uint64_t onm = d.thr_nz ? ~0ull : 0ull;   // K = 0: no bond at all
+    const uint64_t bondm = d.thr_nz ? validm : 0ull;   // K = 0: no bond at all
     const bool even_L = (L & 1u) == 0;
     const bool q2 = d.q == 2;
     uint32_t* rl = RL[wave];
@@ -430,14 +430,14 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         }
         // equal-spin masks and draw masks as wave ballots; a bond needs both
         const uint64_t EX0 = ballot(s0 == s0r) & validm, EY0 = ballot(s0 == s1) & validm;
-        const uint64_t BX0 = EX0 & ballot(wx0 <= d.thr_m1) & onm;
-        const uint64_t BY0 = EY0 & ballot(wy0 <= d.thr_m1) & onm;
+        const uint64_t BX0 = EX0 & ballot(wx0 <= d.thr_m1) & bondm;
+        const uint64_t BY0 = EY0 & ballot(wy0 <= d.thr_m1) & bondm;
         uint64_t EX1 = 0, EY1 = 0, BX1 = 0, BY1 = 0;
         if (two) {
             EX1 = ballot(s1 == s1r) & validm;
             EY1 = ballot(s1 == s2) & validm;
-            BX1 = EX1 & ballot(wx1 <= d.thr_m1) & onm;
-            BY1 = EY1 & ballot(wy1 <= d.thr_m1) & onm;
+            BX1 = EX1 & ballot(wx1 <= d.thr_m1) & bondm;
+            BY1 = EY1 & ballot(wy1 <= d.thr_m1) & bondm;
         }
         if (lane == 0) {
             rb[r][0] = BX0;
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         // the site's entry is its label or, after path halving, an ancestor of it
         const uint32_t first_prov = lds_ld(&P[r0 * TX + x]);
         if (uq.n > QCAP - 64) drain(uq, P, lane, bad);
-        enqueue(uq, lane_in(V & ~R) && up != first_prov, up, first_prov);
+        enqueue(uq, V & ~R, up, first_prov);
     }
     drain(uq, P, lane, bad);
 
