@@ -76,6 +76,17 @@ __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_in
 // kernels where work selected by it (descriptor loads) should stay scalar.
 __device__ __forceinline__ uint32_t wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
+// Sum over the wave of a per-lane value below 2^BITS, bit plane by bit plane
+// (one ballot per plane: cheaper than 64 atomics on one LDS word).
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_sum_small(uint32_t v)
+{
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < BITS; ++k) s += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((v >> k) & 1u)) << k;
+    return s;
+}
+
 // Number of set bits of a wave-uniform mask below this lane.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 {
@@ -391,7 +402,10 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     const bool q2 = d.q == 2;
     uint32_t* rl = RL[wave];
     UnionQueue uq{UQ[wave], &UQT[wave], 0u};
-    uint32_t n_unsat = 0, n_active = 0, n_ones = 0;
+    // measurement: equal-spin pairs counted per wave (scalar), q = 2 spins
+    // summed per lane (column), active bonds counted from the bond words
+    uint32_t n_eq = 0, ones = 0;
+    const uint32_t vbyte = vx ? 0xFFu : 0u;
     uint32_t lp = 0;
     const PhiloxKeys ks = philox_keys_v(d.key0, d.key1);
     bool bad = false;   // this lane met a corrupted forest
@@ -461,25 +475,23 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
             vprev = BY1;
         }
 
-        if (meas) {
-            n_active += popc64(BX0) + popc64(BY0) + popc64(BX1) + popc64(BY1);
-            if (meas_prev) {
-                n_unsat += popc64(validm & ~EX0) + popc64(validm & ~EY0);
-                if (q2) n_ones += popc64(ballot(s0 != 0u) & validm);
-                else count_states(hist, d.q, lane, vx, s0);
-                if (two) {
-                    n_unsat += popc64(validm & ~EX1) + popc64(validm & ~EY1);
-                    if (q2) n_ones += popc64(ballot(s1 != 0u) & validm);
-                    else count_states(hist, d.q, lane, vx, s1);
-                }
+        if (meas_prev) {
+            n_eq += popc64(EX0) + popc64(EY0) + popc64(EX1) + popc64(EY1);   // EX1, EY1 are 0 without row r+1
+            if (q2) ones += (s0 & vbyte) + (s1 & (two ? vbyte : 0u));
+            else {
+                count_states(hist, d.q, lane, vx, s0);
+                if (two) count_states(hist, d.q, lane, vx, s1);
             }
         }
     }
     seam[wave][lane] = lp;
-    if (meas && lane == 0) {
-        atomicAdd(&tot[0], n_unsat);
-        atomicAdd(&tot[1], n_active);
-        if (q2 && n_ones) atomicAdd(&hist[1], n_ones);
+    if (meas_prev) {
+        // every site of the strip owns two bonds
+        if (lane == 0 && r0 < r1) atomicAdd(&tot[0], 2u * w * (r1 - r0) - n_eq);
+        if (q2) {
+            const uint32_t n1 = wave_sum_small<6>(ones);   // a lane counts at most TY / 4 <= 32 rows
+            if (lane == 0 && n1) atomicAdd(&hist[1], n1);
+        }
     }
     __syncthreads();
 
@@ -500,9 +512,14 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     // Tile record: bond words (tile-major), crossing-bond masks.
     gptr<uint32_t> rec = glb(d.edges) + (size_t)tile * edge_words(TY);
     gptr<uint64_t> bw = glb(d.bonds) + (size_t)tile * 2 * TY;
-    for (uint32_t j = tid; j < 2 * TY; j += 256) {
-        const uint32_t r = j % TY;
-        if (r < h) bw[j] = rb[r][j / TY];
+    for (uint32_t j0 = 0; j0 < 2 * TY; j0 += 256) {
+        const uint32_t j = j0 + tid, r = j % TY;
+        const uint64_t word = (j < 2 * TY && r < h) ? rb[r][j / TY] : 0ull;
+        if (j < 2 * TY && r < h) bw[j] = word;
+        if (meas) {
+            const uint32_t n = wave_sum_small<7>(popc64(word));   // active bonds
+            if (lane == 0 && n) atomicAdd(&tot[1], n);
+        }
     }
     if (wave == 0) {
         for (uint32_t j = 0; j < TY; j += 64) {
