@@ -405,6 +405,8 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     // measurement: equal-spin pairs counted per wave (scalar), q = 2 spins
     // summed per lane (column), active bonds counted from the bond words
     uint32_t n_eq = 0, ones = 0;
+    const bool q4 = !q2 && d.q <= 4;   // states 1..3 counted per wave in scalars
+    uint32_t c1 = 0, c2 = 0, c3 = 0;
     const uint32_t vbyte = vx ? 0xFFu : 0u;
     uint32_t lp = 0;
     const PhiloxKeys ks = philox_keys_v(d.key0, d.key1);
@@ -478,7 +480,12 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         if (meas_prev) {
             n_eq += popc64(EX0) + popc64(EY0) + popc64(EX1) + popc64(EY1);   // EX1, EY1 are 0 without row r+1
             if (q2) ones += (s0 & vbyte) + (s1 & (two ? vbyte : 0u));
-            else {
+            else if (q4) {
+                const uint64_t v1 = two ? validm : 0ull;
+                c1 += popc64(ballot(s0 == 1u) & validm) + popc64(ballot(s1 == 1u) & v1);
+                c2 += popc64(ballot(s0 == 2u) & validm) + popc64(ballot(s1 == 2u) & v1);
+                c3 += popc64(ballot(s0 == 3u) & validm) + popc64(ballot(s1 == 3u) & v1);
+            } else {
                 count_states(hist, d.q, lane, vx, s0);
                 if (two) count_states(hist, d.q, lane, vx, s1);
             }
@@ -491,6 +498,11 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         if (q2) {
             const uint32_t n1 = wave_sum_small<6>(ones);   // a lane counts at most TY / 4 <= 32 rows
             if (lane == 0 && n1) atomicAdd(&hist[1], n1);
+        }
+        if (q4 && lane == 0) {
+            atomicAdd(&hist[1], c1);
+            atomicAdd(&hist[2], c2);
+            atomicAdd(&hist[3], c3);
         }
     }
     __syncthreads();
