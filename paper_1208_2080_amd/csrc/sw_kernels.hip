@@ -799,15 +799,32 @@ __global__ __launch_bounds__(256) void k_measure(const LatDesc* descs, const Wor
     __syncthreads();
     const uint32_t x = lane;
     const bool vx = x < w;
+    const uint64_t validm = (w == 64) ? ~0ull : ((1ull << w) - 1ull);
     const uint32_t r0 = wave * RPW, r1 = min(h, r0 + RPW);
-    uint32_t n_unsat = 0;
+    // unequal pairs and states 1..3 counted per wave in scalars (q <= 4),
+    // other q through the shared histogram
+    const bool q4 = d.q <= 4;
+    uint32_t n_unsat = 0, c1 = 0, c2 = 0, c3 = 0;
     for (uint32_t r = r0; r < r1; ++r) {
         const uint8_t* row = sp + r * SPW;
         const uint32_t s = row[x], sr = row[x + 1], sd = row[SPW + x];
-        n_unsat += popc64(ballot(vx && s != sr)) + popc64(ballot(vx && s != sd));
-        count_states(hist, d.q, lane, vx, s);
+        n_unsat += popc64(ballot(s != sr) & validm) + popc64(ballot(s != sd) & validm);
+        if (q4) {
+            c1 += popc64(ballot(s == 1u) & validm);
+            c2 += popc64(ballot(s == 2u) & validm);
+            c3 += popc64(ballot(s == 3u) & validm);
+        } else {
+            count_states(hist, d.q, lane, vx, s);
+        }
     }
-    if (lane == 0) atomicAdd(&tot, n_unsat);
+    if (lane == 0) {
+        atomicAdd(&tot, n_unsat);
+        if (q4) {
+            atomicAdd(&hist[1], c1);
+            atomicAdd(&hist[2], c2);
+            atomicAdd(&hist[3], c3);
+        }
+    }
     __syncthreads();
     int64_t* rp = ring_record(d, t, blockIdx.x % NCOPY);
     if (tid == 0) atomic_add_i64(&rp[0], tot);
