@@ -56,6 +56,7 @@ class _Resident:
     admitted: float
     last: float
     done: int = 0
+    unread: int = 0            # sweeps done whose observables are still only on the device
     rows: list = dataclasses.field(default_factory=list)
     lat: list = dataclasses.field(default_factory=list)
 
@@ -82,6 +83,9 @@ class GpuBackend:
     def step(self, handles, n_each):
         self.group.sweep(handles, n_each)
 
+    def sync(self):
+        self.group.stream.synchronize()
+
     def measure(self, handle, first: int, n: int) -> np.ndarray:
         return handle.measure(first, n)
 
@@ -99,15 +103,18 @@ class SwServer:
     """Continuous batching under an HBM budget; see the module docstring."""
 
     def __init__(self, backend, hbm_budget: int, max_jobs: int, max_tiles: int, step_sweeps: int = 20,
-                 clock=time.perf_counter):
-        if step_sweeps < 1 or max_jobs < 1:
-            raise ValueError("step_sweeps and max_jobs must be positive")
+                 measure_every: int = 8, clock=time.perf_counter):
+        if step_sweeps < 1 or max_jobs < 1 or measure_every < 1:
+            raise ValueError("step_sweeps, measure_every and max_jobs must be positive")
         self.backend = backend
         self.hbm_budget = int(hbm_budget)
         self.max_jobs = int(max_jobs)
         self.max_tiles = int(max_tiles)
         self.step_sweeps = int(step_sweeps)
-        self.obs_capacity = self.step_sweeps + 1
+        # observables are copied out every `measure_every` steps (and when a job
+        # ends): the ring keeps that many steps of sweeps
+        self.measure_every = int(measure_every)
+        self.obs_capacity = self.step_sweeps * self.measure_every + 1
         self.clock = clock
         self.peak_bytes = 0
         self.steps = 0
@@ -160,14 +167,18 @@ class SwServer:
             members = list(resident.values())
             n_each = [min(self.step_sweeps, r.job.sweeps - r.done) for r in members]
             self.backend.step([r.handle for r in members], n_each)
-            for r, n in zip(members, n_each):
-                r.rows.append(self.backend.measure(r.handle, r.done, n))
-                r.done += n
+            self.backend.sync()
             te = now()
             self.steps += 1
             for r, n in zip(members, n_each):
+                r.done += n
+                r.unread += n
                 r.lat.append((te - r.last) / n)
                 r.last = te
+                # copy the observables out before the ring could overwrite them
+                if r.done == r.job.sweeps or r.unread + self.step_sweeps > self.obs_capacity - 1:
+                    r.rows.append(self.backend.measure(r.handle, r.done - r.unread, r.unread))
+                    r.unread = 0
             # retire finished jobs
             for r in members:
                 if r.done == r.job.sweeps:

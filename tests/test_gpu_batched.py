@@ -96,8 +96,9 @@ def test_server_jobs_identical_alone_and_in_the_mix():
     jobs = [serve.Job(id=j["id"], L=j["L"], q=j["q"], K=j["K"], seed=j["seed"], sweeps=j["sweeps"],
                       arrival=j["arrival"]) for j in raw]
     backend = serve.GpuBackend(max_jobs=6, max_tiles=4096)
-    budget = 4 * max(backend.footprint(j, 9) for j in jobs)
-    srv = serve.SwServer(backend, hbm_budget=budget, max_jobs=6, max_tiles=4096, step_sweeps=8)
+    srv = serve.SwServer(backend, hbm_budget=1 << 40, max_jobs=6, max_tiles=4096, step_sweeps=8, measure_every=3)
+    budget = 4 * max(backend.footprint(j, srv.obs_capacity) for j in jobs)
+    srv.hbm_budget = budget
     results, stats = srv.run(jobs, realtime=True)
     say(f"server stats {stats}")
     assert len(results) == len(jobs) and srv.peak_bytes <= budget

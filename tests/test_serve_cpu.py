@@ -38,8 +38,12 @@ class OracleBackend:
         for h, n in zip(handles, n_each):
             h.pending.append(h.run(n))
 
+    def sync(self):
+        pass
+
     def measure(self, h, first, n):
-        rows = h.pending.pop(0)
+        rows = np.concatenate(h.pending, axis=0)
+        h.pending = []
         assert rows.shape[0] == n and h.t == first + n
         return rows
 
@@ -56,12 +60,14 @@ def _jobs(n=14, seed=5):
                       arrival=j["arrival"]) for j in raw]
 
 
-@pytest.mark.parametrize("step", [1, 7, 64])
-def test_results_identical_to_jobs_alone(step):
+@pytest.mark.parametrize("step,every", [(1, 1), (7, 3), (64, 8), (5, 2)])
+def test_results_identical_to_jobs_alone(step, every):
     jobs = _jobs()
     backend = OracleBackend()
-    budget = 3 * max(backend.footprint(j, step + 1) for j in jobs)
-    srv = serve.SwServer(backend, hbm_budget=budget, max_jobs=4, max_tiles=10_000, step_sweeps=step)
+    srv = serve.SwServer(backend, hbm_budget=1 << 40, max_jobs=4, max_tiles=10_000, step_sweeps=step,
+                         measure_every=every)
+    budget = 3 * max(backend.footprint(j, srv.obs_capacity) for j in jobs)
+    srv.hbm_budget = budget
     results, stats = srv.run(jobs, realtime=False)
     assert sorted(results) == [j.id for j in sorted(jobs, key=lambda j: j.id)]
     assert srv.peak_bytes <= budget and backend.max_live <= 4
@@ -80,7 +86,7 @@ def test_fifo_admission_never_overtakes_the_head():
             serve.Job(id=2, L=8, q=2, K=0.9, seed=3, sweeps=5)]
     backend = OracleBackend()
     budget = backend.footprint(jobs[0], 6) + backend.footprint(jobs[2], 6)   # 0 and 2 fit, not 0 and 1
-    srv = serve.SwServer(backend, hbm_budget=budget, max_jobs=8, max_tiles=10_000, step_sweeps=5)
+    srv = serve.SwServer(backend, hbm_budget=budget, max_jobs=8, max_tiles=10_000, step_sweeps=5, measure_every=1)
     results, _ = srv.run(jobs, realtime=False)
     # job 2 is small enough to fit beside job 0 but must not overtake job 1
     assert results[1].admitted <= results[2].admitted
