@@ -195,23 +195,22 @@ int check_device_error(const LatDesc& d, hipStream_t s)
 int read_ring(const LatDesc& d, size_t N, hipStream_t s, uint32_t first, uint32_t n, int64_t* out)
 {
     if (n == 0) return SW_OK;
-    // Only the q + 1 used words of every partial copy cross the bus: one
-    // strided copy (pitch = the copy stride) per contiguous piece of the ring.
-    const size_t R = ring_stride(d.q), rec = (size_t)NCOPY * R, used = d.q + 1;
-    std::vector<int64_t> buf((size_t)n * NCOPY * used);
+    // Whole records in at most two contiguous copies (a strided copy of only
+    // the used words would move fewer bytes but in many tiny pieces).
+    const size_t R = ring_stride(d.q), rec = (size_t)NCOPY * R;
+    std::vector<int64_t> buf((size_t)n * rec);
     const uint32_t slot0 = first % d.cap;
     const uint32_t n1 = std::min<uint32_t>(n, d.cap - slot0);
-    HIP_TRY(hipMemcpy2DAsync(buf.data(), used * 8, d.ring + (size_t)slot0 * rec, R * 8, used * 8,
-                             (size_t)n1 * NCOPY, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(buf.data(), d.ring + (size_t)slot0 * rec, (size_t)n1 * rec * 8, hipMemcpyDeviceToHost, s));
     if (n1 < n)
-        HIP_TRY(hipMemcpy2DAsync(buf.data() + (size_t)n1 * NCOPY * used, used * 8, d.ring, R * 8, used * 8,
-                                 (size_t)(n - n1) * NCOPY, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(buf.data() + (size_t)n1 * rec, d.ring, (size_t)(n - n1) * rec * 8,
+                               hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (uint32_t k = 0; k < n; ++k) {
         int64_t* row = out + (size_t)k * (2 + d.q);
         std::memset(row, 0, (2 + d.q) * 8);
         for (uint32_t cpy = 0; cpy < NCOPY; ++cpy) {
-            const int64_t* r = buf.data() + ((size_t)k * NCOPY + cpy) * used;
+            const int64_t* r = buf.data() + (size_t)k * rec + (size_t)cpy * R;
             row[0] += r[0];
             row[1] += r[1];
             for (uint32_t c = 1; c < d.q; ++c) row[2 + c] += r[1 + c];
