@@ -688,9 +688,11 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
     const gptr<uint32_t> lab = glb(d.lab);
     bool bad = false;
 
-    // Full tiles (the common case) need no masks for columns or rows outside.
-    auto body = [&](auto full) {
+    // Full tiles (the common case) need no masks for columns or rows outside;
+    // a power-of-two L divides by a shift.
+    auto body = [&](auto full, auto pow2) {
         constexpr bool FULL = decltype(full)::value;
+        constexpr bool POW2 = decltype(pow2)::value;
         const bool vcol = FULL || col < w;
         uint32_t v[PER];
 #pragma unroll
@@ -709,12 +711,14 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
             const uint32_t gi = __umul24(y0 + r, L) + x0 + col;
             const uint32_t vv = v[j];
             // tile coordinates of the label (meaningless, and rejected, outside the tile)
-            const uint32_t vy = div_L(d, vv);
-            const uint32_t dy = vy - y0, dx = (vv - __umul24(vy, L)) - x0;
+            const uint32_t vy = POW2 ? vv >> d.log2L : div_L(d, vv);
+            const uint32_t dy = vy - y0, dx = (POW2 ? (vv & (L - 1u)) : vv - __umul24(vy, L)) - x0;
             const bool term = vcol && (vv == gi || dy >= (FULL ? TY : h) || dx >= (FULL ? TX : w));
             if (vcol) E[li] = term ? vv : dy * TX + dx;
             const uint64_t m = ballot(term);
-            my_list[term ? nterm + lanes_below(m) : PER * TX + lane] = (uint16_t)li;
+            // terminals append to the list, the other lanes write their scratch slot
+            const uint32_t at_list = nterm + lanes_below(m), at_scratch = PER * TX + lane;
+            my_list[term ? at_list : at_scratch] = (uint16_t)li;
             nterm = __builtin_amdgcn_readfirstlane(nterm + popc64(m));
         }
 
@@ -757,8 +761,12 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
             if (vcol && (FULL || r < h)) glb(d.s)[(size_t)(y0 + r) * L + x0 + col] = (uint8_t)e[j];
         }
     };
-    if (w == TX && h == TY) body(std::true_type{});
-    else body(std::false_type{});
+    if (w == TX && h == TY) {
+        if (d.log2L) body(std::true_type{}, std::true_type{});
+        else body(std::true_type{}, std::false_type{});
+    } else {
+        body(std::false_type{}, std::false_type{});
+    }
     if (bad) flag_error(d.err);
 
     // The ring record of the next sweep starts from zero.

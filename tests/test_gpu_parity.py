@@ -70,7 +70,7 @@ def test_small_config_other_seeds(seed):
     compare_sweeps(c["L"], c["q"], c["K"], seed, True, sweeps=60, labels_every=5)
 
 
-@pytest.mark.parametrize("L", [2, 3, 5, 17, 63, 65, 127, 128, 129, 130, 200, 255, 257, 300])
+@pytest.mark.parametrize("L", [2, 3, 5, 17, 63, 65, 127, 128, 129, 130, 192, 200, 255, 257, 300, 320, 384])
 def test_ragged_sizes(L):
     compare_sweeps(L, 2, wl.critical_coupling(2), seed=L, sweeps=8)
 
