@@ -555,38 +555,34 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     }
     __syncthreads();
 
-    // Final tile-local labels as global site indices.  Lane i collects the
-    // labels of the left and right columns in strip row i; the first and last
-    // rows of the strip are kept for the top and bottom edges of the tile.
-    // Entries of columns outside the tile point at labels inside it, so their
-    // walks are harmless; only their stores are masked (full-width tiles, the
-    // common case, need no mask at all).
-    uint32_t colL = 0, colR = 0, gfirst = 0, glast = 0;
-    auto final_labels = [&](auto full) {
+    // Labels out: every site gets its union-find parent as a global site index
+    // (a smaller site of its tile-local cluster, or itself for the tile-local
+    // root); the flip follows these pointers inside the tile.  Entries of
+    // columns outside the tile are never stored (full-width tiles, the common
+    // case, need no mask at all).
+    // a site index fits 32 bits (N <= 2^32) and y, L fit 24 bits
+    auto global_index = [&](uint32_t la) { return __umul24(y0 + la / TX, L) + x0 + la % TX; };
+    auto parents_out = [&](auto full) {
         constexpr bool FULL = decltype(full)::value;
         const bool vs = FULL || vx;
         for (uint32_t r = r0; r < r1; ++r) {
-            const uint32_t i = r - r0;
-            const uint32_t la = lds_root(P, r * TX + x, bad);
-            // a site index fits 32 bits (N <= 2^32) and y, L fit 24 bits
-            const uint32_t ga = __umul24(y0 + la / TX, L) + x0 + la % TX;
+            const uint32_t ga = global_index(P[r * TX + x]);
             const gptr<uint32_t> lrow = glb(d.lab) + (size_t)(y0 + r) * L + x0;
             if (vs) lrow[x] = ga;
-            const uint32_t gl = __builtin_amdgcn_readlane(ga, 0), gr = __builtin_amdgcn_readlane(ga, w - 1);
-            colL = (lane == i) ? gl : colL;
-            colR = (lane == i) ? gr : colR;
-            gfirst = (r == r0) ? ga : gfirst;
-            glast = ga;
         }
     };
-    if (w == TX) final_labels(std::true_type{});
-    else final_labels(std::false_type{});
+    if (w == TX) parents_out(std::true_type{});
+    else parents_out(std::false_type{});
+    // The tile's edges for the merge carry tile-local roots: lane i walks the
+    // left and right sites of strip row i; the first and last strips walk the
+    // top and bottom rows.
     if (r0 < r1 && lane < r1 - r0) {
-        rec[8 + r0 + lane] = colR;
-        rec[8 + TY + r0 + lane] = colL;
+        const uint32_t r = r0 + lane;
+        rec[8 + r] = global_index(lds_root(P, r * TX + w - 1, bad));
+        rec[8 + TY + r] = global_index(lds_root(P, r * TX, bad));
     }
-    if (r0 == 0 && r0 < r1 && vx) rec[8 + 2 * TY + TX + x] = gfirst;   // top row
-    if (r1 == h && r0 < r1 && vx) rec[8 + 2 * TY + x] = glast;         // bottom row
+    if (r0 == 0 && r0 < r1 && vx) rec[8 + 2 * TY + TX + x] = global_index(lds_root(P, x, bad));   // top row
+    if (r1 == h && r0 < r1 && vx) rec[8 + 2 * TY + x] = global_index(lds_root(P, (h - 1) * TX + x, bad));   // bottom
     if (bad) flag_error(d.err);
 
     if (meas) {

@@ -2,9 +2,10 @@
 //
 // Per lattice (site i = y*L + x, row-major):
 //   spins   uint8  [N]
-//   labels  uint32 [N]        after a sweep: non-root sites hold the smallest
-//                             site index of their tile-local cluster; tile-local
-//                             roots hold their parent in the global forest
+//   labels  uint32 [N]        after a sweep: every site holds a smaller site of
+//                             its tile-local cluster (its union-find parent
+//                             within the tile); tile-local roots hold their
+//                             parent in the global forest (themselves if none)
 //   bonds   uint64 [tiles][2][TY]  tile-major bond words: tile t, plane p (0: +x,
 //                             1: +y), row r; bit x = bond of site (x0 + x, y0 + r)
 //   edges   uint32 [tiles][EDGE_WORDS(TY)]  per-tile boundary record (below)
