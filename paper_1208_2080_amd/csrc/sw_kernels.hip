@@ -555,9 +555,9 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     }
     __syncthreads();
 
-    // Labels out: every site gets its union-find parent as a global site index
-    // (a smaller site of its tile-local cluster, or itself for the tile-local
-    // root); the flip follows these pointers inside the tile.  Entries of
+    // Labels out: every site gets its union-find grandparent as a global site
+    // index (a smaller site of its tile-local cluster, or itself for the
+    // tile-local root); the flip follows these pointers inside the tile.  Entries of
     // columns outside the tile are never stored (full-width tiles, the common
     // case, need no mask at all).
     // a site index fits 32 bits (N <= 2^32) and y, L fit 24 bits
@@ -566,7 +566,8 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
         constexpr bool FULL = decltype(full)::value;
         const bool vs = FULL || vx;
         for (uint32_t r = r0; r < r1; ++r) {
-            const uint32_t ga = global_index(P[r * TX + x]);
+            // the grandparent: one more read here saves the flip a longer walk
+            const uint32_t ga = global_index(P[P[r * TX + x]]);
             const gptr<uint32_t> lrow = glb(d.lab) + (size_t)(y0 + r) * L + x0;
             if (vs) lrow[x] = ga;
         }
