@@ -1,7 +1,7 @@
 // HIP kernels of one Swendsen-Wang sweep for gfx950, plus their launchers.
 //
 // One sweep is three launches over the tiles of the lattice (TX = 64 columns
-// by TY rows, one 256-thread workgroup of four waves per tile, one column per
+// by TY rows, one workgroup of four waves (eight for 128 rows) per tile, one column per
 // lane):
 //   k_bond_label  bonds (Sec. 2 step (1)) + tile-local cluster labelling
 //                 + measurement of the configuration the bonds were drawn on
@@ -29,6 +29,13 @@ namespace {
 constexpr uint32_t LDS_CAP = 1u << 15;     // cap of union retries in LDS (> sites of a tile)
 constexpr uint32_t UNITE_CAP = 1u << 12;   // cap of union retries in the global forest
 constexpr uint32_t SPW = TX + 4;           // LDS row stride of staged spins (bytes)
+
+// Waves of a tile workgroup: every wave owns 16 rows of a 64- or 128-row tile
+// (8 of a 32-row tile), one column per lane.
+template <int TY>
+constexpr uint32_t waves_of() { return TY == 128 ? 8u : 4u; }
+template <int TY>
+constexpr uint32_t threads_of() { return 64u * waves_of<TY>(); }
 
 struct TileGeom {
     uint32_t tx, ty, x0, y0, w, h;
@@ -226,14 +233,15 @@ __device__ uint32_t g_root(gptr<uint32_t> lab, uint32_t x, bool& bad)
 template <int TY>
 __device__ __forceinline__ void stage_spins(uint8_t* sp, const LatDesc& d, const TileGeom& g, uint32_t tid)
 {
+    constexpr uint32_t NT = threads_of<TY>();
     const uint32_t L = d.L, w = g.w, h = g.h;
     const uint32_t yb = (g.y0 + h == L) ? 0u : g.y0 + h;          // row below the tile
     const uint32_t xh = (g.x0 + w == L) ? 0u : g.x0 + w;          // column right of the tile
     if ((L & 3u) == 0) {
-        // rows start 4-byte aligned (w is then a multiple of 4): 16 rows per pass
+        // rows start 4-byte aligned (w is then a multiple of 4): NT / 16 rows per pass
         const uint32_t c = tid & 15u, dw = w >> 2;
 #pragma unroll
-        for (uint32_t rr = 0; rr <= (uint32_t)TY; rr += 16) {
+        for (uint32_t rr = 0; rr <= (uint32_t)TY; rr += NT / 16) {
             const uint32_t r = rr + (tid >> 4);
             if (r <= h && c < dw) {
                 const uint32_t y = (r < h) ? g.y0 + r : yb;
@@ -244,7 +252,7 @@ __device__ __forceinline__ void stage_spins(uint8_t* sp, const LatDesc& d, const
     } else {
         const uint32_t c = tid & 63u;
 #pragma unroll 4
-        for (uint32_t rr = 0; rr <= (uint32_t)TY; rr += 4) {
+        for (uint32_t rr = 0; rr <= (uint32_t)TY; rr += NT / 64) {
             const uint32_t r = rr + (tid >> 6);
             if (r <= h && c < w) {
                 const uint32_t y = (r < h) ? g.y0 + r : yb;
@@ -252,7 +260,7 @@ __device__ __forceinline__ void stage_spins(uint8_t* sp, const LatDesc& d, const
             }
         }
     }
-    for (uint32_t r = tid; r <= h; r += 256) {
+    for (uint32_t r = tid; r <= h; r += NT) {
         const uint32_t y = (r < h) ? g.y0 + r : yb;
         sp[r * SPW + w] = glb(d.s)[(size_t)y * L + xh];
     }
@@ -286,10 +294,13 @@ __device__ __forceinline__ void atomic_add_i64(int64_t* p, uint64_t v)
 // Per-wave queue of pending unions (pairs of provisional labels, 16 bits
 // each).  Row labelling never reads the union-find, so unions can wait and
 // then run with every lane busy instead of one lane of a diverged wave.
-constexpr uint32_t QCAP = 256;   // a two-row step queues at most 128
+// Union queue slots per wave (a two-row step queues at most 128); a little
+// smaller for 128-row tiles so that three of their workgroups fit a CU's LDS.
+template <int TY>
+constexpr uint32_t qcap_of() { return TY == 128 ? 224u : 256u; }
 
 struct UnionQueue {
-    uint32_t* q;       // QCAP slots in LDS
+    uint32_t* q;       // the wave's slots in LDS
     uint32_t* trash;   // an LDS word for lanes with nothing to store
     uint32_t n;        // wave-uniform fill
 };
@@ -361,19 +372,21 @@ __device__ __forceinline__ uint32_t row_labels(uint32_t* P, uint32_t* rl, UnionQ
 // flags bit 0: also measure the configuration the bonds are drawn on (the
 // result of the previous sweep, t - 1).
 template <int TY>
-__global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const WorkItem* map, uint32_t k,
+__global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* descs, const WorkItem* map, uint32_t k,
                                                    uint32_t flags)
 {
-    constexpr uint32_t RPW = TY / 4;   // rows per wave (even)
+    constexpr uint32_t NW = waves_of<TY>(), NT = threads_of<TY>();
+    constexpr uint32_t RPW = TY / NW;  // rows per wave (even)
+    constexpr uint32_t QCAP = qcap_of<TY>();
     __shared__ uint32_t P[TY * TX];    // union-find over the tile's sites
     __shared__ __align__(16) uint8_t sp[(TY + 1) * SPW];
     __shared__ uint64_t rb[TY][2];     // per row: +x bond word, +y bond word
     // per wave: the label of every run of a row; once a wave has left its
     // strip, its row holds the labels of the strip's last row (the seam)
-    __shared__ uint32_t RL[4][65];     // [64]: scratch word of lanes with nothing to store
-    __shared__ uint32_t UQT[4];        // scratch words of the union queues
+    __shared__ uint32_t RL[NW][65];    // [64]: scratch word of lanes with nothing to store
+    __shared__ uint32_t UQT[NW];       // scratch words of the union queues
     uint32_t(*const seam)[65] = RL;
-    __shared__ uint32_t UQ[4][QCAP];   // per wave: pending unions
+    __shared__ uint32_t UQ[NW][QCAP];  // per wave: pending unions
     __shared__ uint32_t hist[256];
     __shared__ uint32_t tot[2];
 
@@ -387,7 +400,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     const uint32_t tid = threadIdx.x, wave = wave_id(), lane = tid & 63u;
     const uint32_t L = d.L, w = g.w, h = g.h, x0 = g.x0, y0 = g.y0;
 
-    hist[tid] = 0;
+    if (tid < 256) hist[tid] = 0;
     if (tid < 2) tot[tid] = 0;
     stage_spins<TY>(sp, d, g, tid);
     __syncthreads();
@@ -524,7 +537,7 @@ __global__ __launch_bounds__(256) void k_bond_label(const LatDesc* descs, const 
     // Tile record: bond words (tile-major), crossing-bond masks.
     gptr<uint32_t> rec = glb(d.edges) + (size_t)tile * edge_words(TY);
     gptr<uint64_t> bw = glb(d.bonds) + (size_t)tile * 2 * TY;
-    for (uint32_t j0 = 0; j0 < 2 * TY; j0 += 256) {
+    for (uint32_t j0 = 0; j0 < 2 * TY; j0 += NT) {
         const uint32_t j = j0 + tid, r = j % TY;
         const uint64_t word = (j < 2 * TY && r < h) ? rb[r][j / TY] : 0ull;
         if (j < 2 * TY && r < h) bw[j] = word;
@@ -667,11 +680,12 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
 // column); its labels are all loaded first, and its terminals go to a list of
 // its own.
 template <int TY>
-__global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkItem* map, uint32_t k)
+__global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs, const WorkItem* map, uint32_t k)
 {
-    constexpr uint32_t PER = TY / 4;   // rows per wave
+    constexpr uint32_t NW = waves_of<TY>(), NT = threads_of<TY>();
+    constexpr uint32_t PER = TY / NW;  // rows per wave
     __shared__ uint32_t E[TY * TX];
-    __shared__ uint16_t list[4][PER * TX + 64];   // + a scratch slot per lane
+    __shared__ uint16_t list[NW][PER * TX + 64];   // + a scratch slot per lane
 
     LatDesc d;
     uint32_t tile;
@@ -694,14 +708,14 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
         uint32_t v[PER];
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
-            const uint32_t r = wave + 4 * j;
+            const uint32_t r = wave + NW * j;
             v[j] = (vcol && (FULL || r < h)) ? lab[(size_t)(y0 + r) * L + x0 + col] : 0u;
         }
 
         uint32_t nterm = 0;   // wave-uniform
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
-            const uint32_t r = wave + 4 * j;
+            const uint32_t r = wave + NW * j;
             if (!FULL && r >= h) continue;
             const uint32_t li = r * TX + col;
             // site indices fit 32 bits (N <= 2^32) and rows, L fit 24 bits
@@ -740,7 +754,7 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
         uint32_t e[PER];
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
-            const uint32_t r = wave + 4 * j;
+            const uint32_t r = wave + NW * j;
             e[j] = TERM;
             if (vcol && (FULL || r < h)) {
                 uint32_t cur = r * TX + col, v = E[cur];
@@ -754,7 +768,7 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
         }
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
-            const uint32_t r = wave + 4 * j;
+            const uint32_t r = wave + NW * j;
             if (vcol && (FULL || r < h)) glb(d.s)[(size_t)(y0 + r) * L + x0 + col] = (uint8_t)e[j];
         }
     };
@@ -770,7 +784,7 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
     if (d.cap && tile == 0) {
         const uint32_t words = NCOPY * ring_stride(d.q);
         gptr<int64_t> rec = glb(d.ring) + (size_t)((t + 1) % d.cap) * words;
-        for (uint32_t i = tid; i < words; i += 256) rec[i] = 0;
+        for (uint32_t i = tid; i < words; i += NT) rec[i] = 0;
     }
 }
 
@@ -778,10 +792,10 @@ __global__ __launch_bounds__(256) void k_flip(const LatDesc* descs, const WorkIt
 // Measurement of the current configuration into the ring record of sweep
 // counter + k (used after the last sweep of a call).
 template <int TY>
-__global__ __launch_bounds__(256) void k_measure(const LatDesc* descs, const WorkItem* map, uint32_t k,
+__global__ __launch_bounds__(threads_of<TY>()) void k_measure(const LatDesc* descs, const WorkItem* map, uint32_t k,
                                                 const uint32_t* n_each)
 {
-    constexpr uint32_t RPW = TY / 4;
+    constexpr uint32_t RPW = TY / waves_of<TY>();
     __shared__ __align__(16) uint8_t sp[(TY + 1) * SPW];
     __shared__ uint32_t hist[256];
     __shared__ uint32_t tot;
@@ -798,7 +812,7 @@ __global__ __launch_bounds__(256) void k_measure(const LatDesc* descs, const Wor
     const uint32_t t = *glb(d.counter) + k;
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
     const uint32_t w = g.w, h = g.h;
-    hist[tid] = 0;
+    if (tid < 256) hist[tid] = 0;
     if (tid == 0) tot = 0;
     stage_spins<TY>(sp, d, g, tid);
     __syncthreads();
@@ -880,13 +894,17 @@ uint32_t init_grid(size_t N)
 }
 }  // namespace
 
-#define SWMI_TY_DISPATCH(TYV, KERNEL, GRID, ...)                                                       \
-    switch (TYV) {                                                                                     \
-    case 32: hipLaunchKernelGGL(KERNEL<32>, dim3(GRID), dim3(256), 0, w.stream, __VA_ARGS__); break;   \
-    case 64: hipLaunchKernelGGL(KERNEL<64>, dim3(GRID), dim3(256), 0, w.stream, __VA_ARGS__); break;   \
-    case 128: hipLaunchKernelGGL(KERNEL<128>, dim3(GRID), dim3(256), 0, w.stream, __VA_ARGS__); break; \
-    default: return hipErrorInvalidValue;                                                              \
+// BLOCK(T): threads per workgroup of the kernel instantiated for T rows.
+#define SWMI_TY_DISPATCH_B(TYV, KERNEL, GRID, BLOCK, ...)                                                    \
+    switch (TYV) {                                                                                         \
+    case 32: hipLaunchKernelGGL(KERNEL<32>, dim3(GRID), dim3(BLOCK(32)), 0, w.stream, __VA_ARGS__); break;    \
+    case 64: hipLaunchKernelGGL(KERNEL<64>, dim3(GRID), dim3(BLOCK(64)), 0, w.stream, __VA_ARGS__); break;    \
+    case 128: hipLaunchKernelGGL(KERNEL<128>, dim3(GRID), dim3(BLOCK(128)), 0, w.stream, __VA_ARGS__); break; \
+    default: return hipErrorInvalidValue;                                                                  \
     }
+#define SWMI_TILE_BLOCK(T) threads_of<T>()
+#define SWMI_FOUR_WAVES(T) 256
+#define SWMI_TY_DISPATCH(TYV, KERNEL, GRID, ...) SWMI_TY_DISPATCH_B(TYV, KERNEL, GRID, SWMI_TILE_BLOCK, __VA_ARGS__)
 
 hipError_t launch_bond_label(const Work& w, uint32_t k, uint32_t flags)
 {
@@ -898,7 +916,7 @@ hipError_t launch_bond_label(const Work& w, uint32_t k, uint32_t flags)
 hipError_t launch_merge(const Work& w)
 {
     if (w.nitems == 0) return hipSuccess;
-    SWMI_TY_DISPATCH(w.ty, k_merge, (w.nitems + 3) / 4, w.descs, w.map, w.nitems);
+    SWMI_TY_DISPATCH_B(w.ty, k_merge, (w.nitems + 3) / 4, SWMI_FOUR_WAVES, w.descs, w.map, w.nitems);
     return hipGetLastError();
 }
 
