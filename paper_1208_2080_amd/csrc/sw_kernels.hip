@@ -1,15 +1,15 @@
 // HIP kernels of one Swendsen-Wang sweep for gfx950, plus their launchers.
 //
 // One sweep is three launches over the tiles of the lattice (TX = 64 columns
-// by TY rows, one workgroup of four waves (eight for 128 rows) per tile, one column per
-// lane):
+// by TY rows; one workgroup per tile, four waves, eight for 128 rows; one
+// column per lane):
 //   k_bond_label  bonds (Sec. 2 step (1)) + tile-local cluster labelling
 //                 + measurement of the configuration the bonds were drawn on
 //   k_merge       joins tile-local clusters across tile edges (global union-find
 //                 with atomicMin, larger root under smaller)
 //   k_flip        every cluster takes the state drawn for its smallest site
-//                 index (Sec. 2 step (3)); each site copies it from its
-//                 tile-local root
+//                 index (Sec. 2 step (3)); each site follows its in-tile
+//                 pointers to a resolved tile-local root
 // plus k_measure after the last sweep of a call, and small helpers.
 #include <hip/hip_runtime.h>
 
