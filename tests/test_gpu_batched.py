@@ -28,7 +28,7 @@ MIX = [dict(L=64, q=2, K=wl.critical_coupling(2), seed=11),
        dict(L=191, q=2, K=float("inf"), seed=18, random_start=False)]
 
 
-@pytest.mark.parametrize("ty", [32, 64])
+@pytest.mark.parametrize("ty", [32, 64, 128])
 def test_batch_sweep_all_matches_oracle(ty):
     say(f"batch sweep_all ty={ty}")
     b = binding.Batch(MIX, obs_capacity=32, tile_rows=ty)
