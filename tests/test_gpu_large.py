@@ -169,3 +169,37 @@ def test_sampled_and_properties_L65536(name):
     say(f"  {checked} of {tried} sampled clusters rebuilt exactly (the rest exceed 2000 sites)")
     assert checked >= 30
     assert W == bx.shape[1]
+
+
+def test_L4096_observables_every_sweep():
+    """L = 4096 for 20 sweeps: int64 observables after every sweep and the final
+    spins against the oracle."""
+    cfg = wl.PLAIN_4096
+    L, q, K, seed = cfg["L"], cfg["q"], cfg["K"], cfg["seed"]
+    n = 20
+    say(f"L={L} q={q} {n} sweeps")
+    lat = binding.Lattice(L, q, K, seed=seed, random_start=cfg["random_start"], obs_capacity=n)
+    lat.sweep(n)
+    ref = oracle.OracleLattice(L, q, K, seed, random_start=cfg["random_start"])
+    rows = ref.run(n)
+    assert np.array_equal(lat.measure(0, n), rows)
+    assert np.array_equal(lat.spins(), ref.s)
+    lat.close()
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_L65536_one_cluster_counts_need_64_bits(q):
+    """K = infinity from the cold start: every bond is active, the whole
+    lattice is one cluster rooted at site 0, so one state holds all 2^32 sites
+    and n_active = 2^33 -- both past 32-bit range."""
+    L, seed = 65536, 5
+    say(f"L={L} q={q} K=inf one cluster")
+    lat = binding.Lattice(L, q, float("inf"), seed=seed, random_start=False, obs_capacity=2)
+    lat.sweep(1)
+    obs = lat.measure(0, 1)[0]
+    s_star = oracle.newspin(seed, 0, 0, q)
+    expect = np.zeros(2 + q, dtype=np.int64)
+    expect[1] = 2 * L * L
+    expect[2 + s_star] = L * L
+    assert np.array_equal(obs, expect), obs
+    lat.close()
