@@ -97,31 +97,6 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __builtin_amdgcn_bal
 
 __device__ __forceinline__ uint32_t popc64(uint64_t v) { return (uint32_t)__popcll(v); }
 
-// Spread the 32 low bits of v to the even bit positions of a 64-bit word.
-__device__ __forceinline__ uint64_t spread_even(uint32_t v)
-{
-    uint64_t x = v;
-    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
-    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
-    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
-    x = (x | (x << 2)) & 0x3333333333333333ull;
-    x = (x | (x << 1)) & 0x5555555555555555ull;
-    return x;
-}
-
-// Lane l of a wave holds sites 2l (even) and 2l+1 (odd) of a 128-site row
-// segment; turn the two 64-bit ballots into the segment's two words.
-__device__ __forceinline__ void interleave_row(uint64_t even, uint64_t odd, uint64_t& w0, uint64_t& w1)
-{
-    w0 = spread_even((uint32_t)even) | (spread_even((uint32_t)odd) << 1);
-    w1 = spread_even((uint32_t)(even >> 32)) | (spread_even((uint32_t)(odd >> 32)) << 1);
-}
-
-// mask of bits 0..b (b in 0..63)
-__device__ __forceinline__ uint64_t upto(uint32_t b) { return (2ull << b) - 1ull; }
-
-__device__ __forceinline__ uint32_t msb64(uint64_t v) { return 63u - (uint32_t)__clzll(v); }
-
 // ----------------------------------------------------------- global memory
 // Pointers read from a descriptor have no known address space; accesses
 // through them would compile to flat instructions, which also hold the LDS
