@@ -100,7 +100,9 @@ def copy_calibration(nbytes: int = 1 << 30):
 
 def batched_vs_plain(n_replicas: int, sweeps: int, tile_rows: int) -> dict:
     """Aggregate flips/ns of independent replicas of uneven L, q, K swept as one
-    batch (one launch per phase, HIP graph) versus one lattice after another."""
+    batch (one launch per phase, HIP graph) versus one lattice after another.
+    Without an explicit tile height the library's autotuner picks it (outside
+    the timed region), and the plain loop uses the same height."""
     import numpy as np
     import torch
     from paper_1208_2080_amd import binding
@@ -108,7 +110,8 @@ def batched_vs_plain(n_replicas: int, sweeps: int, tile_rows: int) -> dict:
 
     reps = wl.batched_replicas(n=n_replicas, sweeps=sweeps)
     flips = sum(r["L"] ** 2 for r in reps) * sweeps
-    b = binding.Batch(reps, obs_capacity=2, tile_rows=tile_rows)
+    b = binding.Batch(reps, obs_capacity=2, tile_rows=tile_rows or "auto")
+    tile_rows = b.tile_rows
     b.sweep_all(2)                                   # warm-up (and graph capture)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -132,8 +135,10 @@ def batched_vs_plain(n_replicas: int, sweeps: int, tile_rows: int) -> dict:
     same = all(np.array_equal(b.spins(i), lat.spins()) for i, lat in enumerate(lats))
     for lat in lats:
         lat.close()
+    b_tuned = b.tuned_ms
     b.close()
-    return {"replicas": n_replicas, "sweeps": sweeps, "sites": flips // sweeps,
+    return {"replicas": n_replicas, "sweeps": sweeps, "sites": flips // sweeps, "tile_rows": tile_rows,
+            "autotune_ms_per_sweep": b_tuned,
             "batched_flips_per_ns": flips / (t_batch * 1e9), "plain_flips_per_ns": flips / (t_plain * 1e9),
             "speedup": t_plain / t_batch, "identical_results": bool(same)}
 

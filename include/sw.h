@@ -148,6 +148,24 @@ int sw_batch_read_spins(sw_batch* b, uint32_t replica, uint8_t* host_out);
 int sw_batch_sweeps_done(const sw_batch* b, uint32_t replica, uint32_t* out);
 int sw_batch_destroy(sw_batch* b);
 
+/* Tile-height autotuner.  The labelling tile height (tile_rows) only splits the
+ * connected-component labelling of Sec. 2 step (2) between the tile-local pass
+ * and the tile-edge merge (the two stages of Sec. 3); spins, labels and
+ * observables do not depend on it (cluster roots are smallest site indices and
+ * every draw is keyed by site and sweep), so it is a pure performance choice.
+ * For each of the n_candidates (1..8) heights in candidates[] (each 32, 64 or
+ * 128), this initialises the n replicas params[] (their own tile_rows is
+ * ignored) in dev_ws, runs `sweeps` (1..4096) untimed sweeps of every replica,
+ * then times `sweeps` more with HIP events on hip_stream, and writes the
+ * fastest height into *tile_rows and, if ms_per_sweep is not NULL, the measured
+ * milliseconds per sweep of candidate c into ms_per_sweep[c].  dev_ws must hold
+ * sw_batch_workspace_bytes() of the replicas at every candidate height (checked
+ * before any launch: SW_ESPACE); its contents are overwritten and no handle
+ * survives the call.  Synchronises the stream. */
+int sw_batch_autotune(const sw_params* params, uint32_t n, const uint32_t* candidates, uint32_t n_candidates,
+                      uint32_t sweeps, void* dev_ws, size_t ws_bytes, void* hip_stream, uint32_t* tile_rows,
+                      double* ms_per_sweep);
+
 /* ----------------------------------------------------------------- groups
  * Continuous batching: one launch per phase over any set of lattices made by
  * sw_init (same tile_rows, same stream), which may change from call to call.

@@ -56,6 +56,8 @@ SIGNATURES = [
     ("sw_batch_read_spins", ctypes.c_int, [_VP, _U32, _VP]),
     ("sw_batch_sweeps_done", ctypes.c_int, [_VP, _U32, ctypes.POINTER(_U32)]),
     ("sw_batch_destroy", ctypes.c_int, [_VP]),
+    ("sw_batch_autotune", ctypes.c_int, [_PP, _U32, _VP, _U32, _U32, _VP, ctypes.c_size_t, _VP,
+                                         ctypes.POINTER(_U32), ctypes.POINTER(ctypes.c_double)]),
     ("sw_tile_count", ctypes.c_int, [_PP, ctypes.POINTER(_U32)]),
     ("sw_group_workspace_bytes", ctypes.c_int, [_U32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_size_t)]),
     ("sw_group_init", ctypes.c_int, [_U32, ctypes.c_uint64, _U32, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
@@ -209,22 +211,60 @@ class Lattice:
             pass
 
 
-class Batch:
-    """Independent replicas of uneven L, q and K swept together, one launch per phase."""
+def _replica_params(replicas, obs_capacity: int, tile_rows: int):
+    arr = (SwParams * len(replicas))()
+    for i, r in enumerate(replicas):
+        arr[i] = make_params(r["L"], r["q"], r["K"], r["seed"], r.get("random_start", True),
+                             r.get("obs_capacity", obs_capacity), tile_rows)
+    return arr
 
-    def __init__(self, replicas, obs_capacity: int = 64, tile_rows: int = 0, device=None, stream=None):
+
+def _batch_bytes(arr) -> int:
+    nbytes = ctypes.c_size_t()
+    _check(lib().sw_batch_workspace_bytes(arr, len(arr), ctypes.byref(nbytes)))
+    return int(nbytes.value)
+
+
+TILE_HEIGHTS = (32, 64, 128)
+
+
+def autotune(replicas, obs_capacity: int = 64, candidates=TILE_HEIGHTS, sweeps: int = 8, device=None,
+             stream=None):
+    """Pick the fastest labelling tile height for this set of replicas (the
+    library times each candidate); returns (height, {height: ms per sweep})."""
+    replicas = [dict(r) for r in replicas]
+    cands = (ctypes.c_uint32 * len(candidates))(*[int(c) for c in candidates])
+    nbytes = max(_batch_bytes(_replica_params(replicas, obs_capacity, int(c))) for c in candidates)
+    device = torch.device("cuda", 0) if device is None else torch.device(device)
+    stream = stream if stream is not None else torch.cuda.Stream(device)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    torch.cuda.current_stream(device).synchronize()   # workspace allocated before first use
+    best = ctypes.c_uint32()
+    ms = (ctypes.c_double * len(candidates))()
+    _check(lib().sw_batch_autotune(_replica_params(replicas, obs_capacity, 0), len(replicas), cands,
+                                   len(candidates), int(sweeps), ctypes.c_void_p(ws.data_ptr()), nbytes,
+                                   ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(best), ms))
+    del ws
+    return int(best.value), {int(c): float(ms[i]) for i, c in enumerate(candidates)}
+
+
+class Batch:
+    """Independent replicas of uneven L, q and K swept together, one launch per phase.
+    tile_rows="auto" lets the library's autotuner pick the tile height first."""
+
+    def __init__(self, replicas, obs_capacity: int = 64, tile_rows=0, device=None, stream=None):
         self.replicas = [dict(r) for r in replicas]
         n = len(self.replicas)
-        arr = (SwParams * n)()
-        for i, r in enumerate(self.replicas):
-            arr[i] = make_params(r["L"], r["q"], r["K"], r["seed"], r.get("random_start", True),
-                                 r.get("obs_capacity", obs_capacity), tile_rows)
-        self.params = arr
-        nbytes = ctypes.c_size_t()
-        _check(lib().sw_batch_workspace_bytes(arr, n, ctypes.byref(nbytes)))
         self.device = torch.device("cuda", 0) if device is None else torch.device(device)
         # a stream of its own (default priority): HIP graphs cannot capture the NULL stream
         self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self.tuned_ms = None
+        if tile_rows == "auto":
+            tile_rows, self.tuned_ms = autotune(self.replicas, obs_capacity, device=self.device, stream=self.stream)
+        self.tile_rows = int(tile_rows)
+        arr = _replica_params(self.replicas, obs_capacity, self.tile_rows)
+        self.params = arr
+        nbytes = ctypes.c_size_t(_batch_bytes(arr))
         self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
         torch.cuda.current_stream(self.device).synchronize()   # workspace allocated before first use
         self._h = ctypes.c_void_p()

@@ -759,6 +759,61 @@ int sw_batch_destroy(sw_batch* b)
     return SW_OK;
 }
 
+int sw_batch_autotune(const sw_params* params, uint32_t n, const uint32_t* candidates, uint32_t n_candidates,
+                      uint32_t sweeps, void* dev_ws, size_t ws_bytes, void* hip_stream, uint32_t* tile_rows,
+                      double* ms_per_sweep)
+{
+    if (!params || !candidates || !tile_rows) return fail(SW_EINVAL, "NULL argument");
+    if (n == 0) return fail(SW_EINVAL, "need at least one replica");
+    if (n_candidates == 0 || n_candidates > 8) return fail(SW_EINVAL, "need 1 to 8 candidate tile heights");
+    if (sweeps == 0 || sweeps > 4096) return fail(SW_EINVAL, "time 1 to 4096 sweeps per candidate");
+    std::vector<sw_params> p(params, params + n);
+    // every candidate is checked (and its workspace sized) before the first launch
+    for (uint32_t c = 0; c < n_candidates; ++c) {
+        const uint32_t ty = candidates[c];
+        if (ty != 32 && ty != 64 && ty != 128) return fail(SW_EINVAL, "candidate tile height %u is not 32, 64 or 128", ty);
+        for (auto& pr : p) pr.tile_rows = ty;
+        size_t need = 0;
+        const int rc = sw_batch_workspace_bytes(p.data(), n, &need);
+        if (rc) return rc;
+        if (!dev_ws || ((uintptr_t)dev_ws % ALIGN) != 0)
+            return fail(SW_ESPACE, "workspace must be a 256-byte aligned device pointer");
+        if (ws_bytes < need) return fail(SW_ESPACE, "tile height %u needs %zu workspace bytes, have %zu", ty, need, ws_bytes);
+    }
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    int rc = SW_OK;
+    uint32_t best = 0;
+    double best_ms = 0.0;
+    for (uint32_t c = 0; c < n_candidates && rc == SW_OK; ++c) {
+        for (auto& pr : p) pr.tile_rows = candidates[c];
+        sw_batch* b = nullptr;
+        rc = sw_batch_init(p.data(), n, dev_ws, ws_bytes, hip_stream, &b);
+        if (rc) break;
+        // one untimed pass (graph capture, caches), then the timed one
+        rc = sw_batch_sweep_all(b, sweeps);
+        if (rc == SW_OK && hipEventRecord(ev[0], b->stream) != hipSuccess) rc = fail(SW_EHIP, "hipEventRecord failed");
+        if (rc == SW_OK) rc = sw_batch_sweep_all(b, sweeps);
+        if (rc == SW_OK && hipEventRecord(ev[1], b->stream) != hipSuccess) rc = fail(SW_EHIP, "hipEventRecord failed");
+        if (rc == SW_OK && hipEventSynchronize(ev[1]) != hipSuccess) rc = fail(SW_EHIP, "hipEventSynchronize failed");
+        float ms = 0.f;
+        if (rc == SW_OK && hipEventElapsedTime(&ms, ev[0], ev[1]) != hipSuccess)
+            rc = fail(SW_EHIP, "hipEventElapsedTime failed");
+        for (uint32_t r = 0; rc == SW_OK && r < n; ++r) rc = check_device_error(b->desc[r], b->stream);
+        (void)sw_batch_destroy(b);
+        if (rc) break;
+        const double per = (double)ms / sweeps;
+        if (ms_per_sweep) ms_per_sweep[c] = per;
+        if (c == 0 || per < best_ms) {
+            best = candidates[c];
+            best_ms = per;
+        }
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc == SW_OK) *tile_rows = best;
+    return rc;
+}
+
 }  // extern "C"
 
 // -------------------------------------------------------------------- groups

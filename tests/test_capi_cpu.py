@@ -85,3 +85,28 @@ def test_init_rejects_bad_workspace_without_touching_the_gpu():
     arr = (binding.SwParams * 2)(binding.make_params(16, 2, 1.0), binding.make_params(40, 3, 0.5))
     assert lib.sw_batch_workspace_bytes(arr, 2, ctypes.byref(n)) == binding.SW_OK
     assert n.value >= _ws(16) + _ws(40, 3)
+
+
+def test_autotune_rejects_bad_arguments_before_any_launch():
+    lib = binding.lib()
+    arr = (binding.SwParams * 2)(binding.make_params(64, 2, 1.0), binding.make_params(100, 3, 0.9))
+    best = ctypes.c_uint32(7)
+    ms = (ctypes.c_double * 3)()
+
+    def call(cands, sweeps=4, ws=0x10000, nbytes=1 << 40, n=2):
+        c = (ctypes.c_uint32 * max(1, len(cands)))(*cands)
+        return lib.sw_batch_autotune(arr, n, c, len(cands), sweeps, ctypes.c_void_p(ws), nbytes, None,
+                                     ctypes.byref(best), ms)
+
+    assert call([32, 48]) == binding.SW_EINVAL            # 48 is not a tile height
+    assert call([]) == binding.SW_EINVAL                  # no candidate
+    assert call([32] * 9) == binding.SW_EINVAL            # too many candidates
+    assert call([64], sweeps=0) == binding.SW_EINVAL
+    assert call([64], n=0) == binding.SW_EINVAL
+    # the workspace must fit the largest candidate layout, and be aligned
+    need = max(binding._batch_bytes(binding._replica_params(
+        [{"L": 64, "q": 2, "K": 1.0, "seed": 1}, {"L": 100, "q": 3, "K": 0.9, "seed": 1}], 2, ty))
+        for ty in (32, 128))
+    assert call([32, 128], nbytes=need - 256) == binding.SW_ESPACE
+    assert call([32, 128], ws=0x10001, nbytes=need) == binding.SW_ESPACE
+    assert best.value == 7                                 # nothing written on failure

@@ -45,6 +45,23 @@ def test_batch_sweep_all_matches_oracle(ty):
     b.close()
 
 
+def test_autotuned_batch_matches_oracle():
+    say("batch autotune")
+    best, ms = binding.autotune(MIX, obs_capacity=32, sweeps=4)
+    assert best in binding.TILE_HEIGHTS
+    assert set(ms) == set(binding.TILE_HEIGHTS) and all(v > 0 for v in ms.values())
+    assert ms[best] == min(ms.values())
+    b = binding.Batch(MIX, obs_capacity=32, tile_rows="auto")
+    assert b.tile_rows in binding.TILE_HEIGHTS and b.tuned_ms[b.tile_rows] == min(b.tuned_ms.values())
+    refs = [oracle.OracleLattice(r["L"], r["q"], r["K"], r["seed"], r.get("random_start", True)) for r in MIX]
+    b.sweep_all(5)
+    for r, ref in enumerate(refs):
+        rows = ref.run(5)
+        assert np.array_equal(b.spins(r), ref.s), f"replica {r}"
+        assert np.array_equal(b.measure(r, 0, 5), rows), f"replica {r}"
+    b.close()
+
+
 def test_batch_uneven_sweep_counts():
     say("batch uneven counts")
     b = binding.Batch(MIX, obs_capacity=32)
