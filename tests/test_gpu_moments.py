@@ -1,0 +1,67 @@
+"""GPU: the moment-ratio check.  Tiny lattices swept in a batch reproduce the
+exactly enumerated <m^2>, <m^4>; the moment ratios of two sizes cross near K_c."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1208_2080_amd import binding, moments
+from paper_1208_2080_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def exact_moments(L, q, K):
+    """<m^2>, <m^4> by enumeration of all q^(L*L) configurations (Eq. (1) weights)."""
+    N = L * L
+    confs = np.array(list(itertools.product(range(q), repeat=N)), dtype=np.int64).reshape(-1, L, L)
+    unsat = (confs != np.roll(confs, -1, axis=2)).sum(axis=(1, 2)) + (confs != np.roll(confs, -1, axis=1)).sum(axis=(1, 2))
+    w = np.exp(-K * (unsat - unsat.min()))
+    e = (np.eye(q) - 1.0 / q) * np.sqrt(q / (q - 1.0))
+    vec = e[confs.reshape(len(confs), N)].sum(axis=1)
+    m2 = (vec * vec).sum(axis=1) / N ** 2
+    return float((w * m2).sum() / w.sum()), float((w * m2 * m2).sum() / w.sum())
+
+
+def test_batched_tiny_lattices_reproduce_exact_moments():
+    cases = [(4, 2), (3, 3)]
+    reps = []
+    for L, q in cases:
+        reps += [dict(L=L, q=q, K=wl.critical_coupling(q), seed=900 + 37 * q + i) for i in range(32)]
+    say(f"moments of {len(reps)} tiny replicas")
+    b = binding.Batch(reps, obs_capacity=1001)
+    b.sweep_all(100)
+    rows = [[] for _ in reps]
+    for c in range(3):
+        b.sweep_all(1000)
+        for r in range(len(reps)):
+            rows[r].append(b.measure(r, 100 + 1000 * c, 1000))
+    b.close()
+    for k, (L, q) in enumerate(cases):
+        pooled = np.concatenate([np.concatenate(rows[r]) for r in range(32 * k, 32 * (k + 1))])
+        mo = moments.moments(pooled, q, n_blocks=32)
+        m2, m4 = exact_moments(L, q, wl.critical_coupling(q))
+        say(f"L={L} q={q}: m2 {mo['m2']:.5f} +- {mo['m2_err']:.5f} (exact {m2:.5f}), "
+            f"m4 {mo['m4']:.5f} +- {mo['m4_err']:.5f} (exact {m4:.5f})")
+        assert abs(mo["m2"] - m2) < 5 * mo["m2_err"]
+        assert abs(mo["m4"] - m4) < 5 * mo["m4_err"]
+        assert mo["m2_err"] < 0.005 * m2
+
+
+def test_moment_ratios_cross_near_Kc():
+    say("moment-ratio crossing, q = 2, L = 16 and 32")
+    res = moments.run(2, [16, 32], [0.97, 0.985, 1.0, 1.015, 1.03], sweeps=50000, therm=500)
+    U = {(p["L"], p["K_over_Kc"]): p["U"] for p in res["points"]}
+    assert U[(32, 0.97)] > U[(16, 0.97)]    # disordered side: the larger lattice is further from order
+    assert U[(32, 1.03)] < U[(16, 1.03)]    # ordered side
+    k = res["crossings"][0]["K_over_Kc"]
+    say(f"crossing at K/K_c = {k}")
+    assert k is not None and abs(k - 1.0) < 0.01

@@ -1,0 +1,92 @@
+"""The moment-ratio analysis on the CPU: the m^2 formula against the vector
+magnetisation summed site by site, exact enumeration of <m^2> and <m^4> on tiny
+lattices against long oracle runs, the infinite-temperature closed form and the
+crossing finder."""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1208_2080_amd import moments
+from paper_1208_2080_amd import workloads as wl
+
+
+def simplex(q):
+    """q unit vectors with pairwise dot product -1/(q-1) (embedded in R^q)."""
+    v = np.eye(q) - 1.0 / q
+    return v * np.sqrt(q / (q - 1.0))
+
+
+def m2_brute(spins, q):
+    M = simplex(q)[spins.ravel()].sum(axis=0)
+    return float(M @ M) / spins.size ** 2
+
+
+@pytest.mark.parametrize("q", [2, 3, 5, 8])
+def test_m2_from_counts_equals_the_summed_vector_magnetisation(q):
+    for seed in range(5):
+        s = wl.random_spins(9, q, seed)
+        if seed == 4:
+            s[:] = 1   # fully ordered
+        counts = np.bincount(s.ravel(), minlength=q)
+        assert moments.m2_from_counts(counts[None, :], q)[0] == pytest.approx(m2_brute(s, q), rel=1e-13, abs=1e-15)
+    assert moments.m2_from_counts(np.full((1, q), 7), q)[0] == 0.0
+
+
+def test_m2_from_counts_at_two_to_the_32_sites():
+    N = 1 << 32
+    assert moments.m2_from_counts(np.array([[N, 0]]), 2)[0] == 1.0
+    assert moments.m2_from_counts(np.array([[N // 2, N // 2]]), 2)[0] == 0.0
+    assert moments.m2_from_counts(np.array([[0, N, 0]]), 3)[0] == 1.0
+    # one site off the balanced q = 2 state: (2/N)^2
+    assert moments.m2_from_counts(np.array([[N // 2 + 1, N // 2 - 1]]), 2)[0] == (2.0 / N) ** 2
+
+
+def exact_moments(L, q, K):
+    """<m^2>, <m^4> by enumerating all q^(L*L) configurations of the periodic
+    L x L lattice with Boltzmann weight exp(-K * n_unsat) (Eq. (1))."""
+    N = L * L
+    confs = np.array(list(itertools.product(range(q), repeat=N)), dtype=np.int64).reshape(-1, L, L)
+    unsat = (confs != np.roll(confs, -1, axis=2)).sum(axis=(1, 2)) + (confs != np.roll(confs, -1, axis=1)).sum(axis=(1, 2))
+    w = np.exp(-K * (unsat - unsat.min()))
+    vec = simplex(q)[confs.reshape(len(confs), N)].sum(axis=1)
+    m2 = (vec * vec).sum(axis=1) / N ** 2
+    return float((w * m2).sum() / w.sum()), float((w * m2 * m2).sum() / w.sum())
+
+
+@pytest.mark.parametrize("L,q", [(4, 2), (3, 3), (3, 4)])
+def test_oracle_moments_match_exact_enumeration_at_Kc(L, q):
+    K = wl.critical_coupling(q)
+    m2, m4 = exact_moments(L, q, K)
+    ref = oracle.OracleLattice(L, q, K, seed=41, random_start=True)
+    ref.run(200)
+    mo = moments.moments(ref.run(40000), q)
+    assert abs(mo["m2"] - m2) < 5 * mo["m2_err"], (mo, m2)
+    assert abs(mo["m4"] - m4) < 5 * mo["m4_err"], (mo, m4)
+    assert mo["m2_err"] < 0.01 * m2
+
+
+@pytest.mark.parametrize("L,q", [(5, 2), (4, 3)])
+def test_infinite_temperature_closed_form(L, q):
+    # K = 0: no bond is ever active, every sweep draws independent uniform spins;
+    # then <|M|^2> = N and <|M|^4> = N^2 + 2 N (N - 1) / (q - 1)
+    N = L * L
+    ref = oracle.OracleLattice(L, q, 0.0, seed=5, random_start=True)
+    mo = moments.moments(ref.run(40000), q)
+    assert abs(mo["m2"] - 1.0 / N) < 5 * mo["m2_err"]
+    U = 1.0 + 2.0 * (N - 1) / ((q - 1.0) * N)
+    assert abs(mo["U"] - U) < 5 * mo["U_err"], (mo["U"], U)
+
+
+def test_zero_temperature_is_ordered():
+    ref = oracle.OracleLattice(6, 3, float("inf"), seed=5, random_start=False)
+    mo = moments.moments(ref.run(50), 3)
+    assert mo["m2"] == 1.0 and mo["U"] == 1.0
+
+
+def test_crossing_finder():
+    K = np.linspace(0.95, 1.05, 11)
+    assert moments.crossing(K, 1.5 - (K - 1), 1.5 - 2 * (K - 1)) == pytest.approx(1.0, abs=1e-12)
+    assert moments.crossing(K, 1.5 - (K - 1.02), 1.5 - 3 * (K - 1.02)) == pytest.approx(1.02, abs=1e-12)
+    assert moments.crossing(K, np.ones(11), np.ones(11) * 2) is None
