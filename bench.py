@@ -143,6 +143,26 @@ def batched_vs_plain(n_replicas: int, sweeps: int, tile_rows: int) -> dict:
             "speedup": t_plain / t_batch, "identical_results": bool(same)}
 
 
+def label_equivalence(lat, sweeps: int, per_launch_ms: dict) -> dict:
+    """The paper's labelling (iterated label equivalence: scan + analysis under
+    a host loop) on the bonds of `sweeps` further sweeps of the bench lattice,
+    against this library's tile union-find + merge on the same lattice."""
+    import numpy as np
+
+    passes, ms, same = [], [], True
+    for _ in range(sweeps):
+        lat.sweep(1)
+        le, n, t = lat.label_equivalence()
+        passes.append(n)
+        ms.append(t)
+        same = same and bool(np.array_equal(le, lat.labels()))
+        del le
+    return {"sweeps": sweeps, "mean_passes": float(np.mean(passes)), "passes": passes,
+            "ms_per_labelling": float(np.mean(ms)), "ms_per_pass": float(np.sum(ms) / np.sum(passes)),
+            "tile_union_find_ms": per_launch_ms["k_bond_label"] + per_launch_ms["k_merge"],
+            "identical_labels": same}
+
+
 def serving(n_jobs: int, capacity_flips_per_ns: float, tile_rows: int, loads=(0.5, 0.9, 1.2)) -> list:
     """The continuous-batching server on Poisson job streams offered at fractions
     of the measured single-lattice capacity (jobs/s = load x flips/s / mean flips
@@ -183,6 +203,9 @@ def main():
                     help="also time 256 uneven replicas batched vs one after another for SWEEPS sweeps")
     ap.add_argument("--serve", type=int, default=0, metavar="JOBS",
                     help="also run the server on JOBS Poisson jobs at 0.5, 0.9 and 1.2 x capacity")
+    ap.add_argument("--label-equivalence", type=int, default=0, metavar="SWEEPS",
+                    help="also label the bonds of SWEEPS further sweeps with the paper's iterated label "
+                         "equivalence (a comparison) and report its passes and time")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -257,6 +280,9 @@ def main():
         "phase_ms_per_sweep": {k: v for k, v in per_launch_ms.items()},
         "sweep_roofline_frac": value * SWEEP_BYTES_PER_SITE / HBM_PEAK_GBS,
     }
+    if args.label_equivalence:
+        print("# iterated label equivalence on the same bonds", file=sys.stderr, flush=True)
+        out["label_equivalence"] = label_equivalence(lat, args.label_equivalence, per_launch_ms)
     lat.close()
     del lat
     torch.cuda.empty_cache()

@@ -120,6 +120,20 @@ int sw_read_labels(sw_lattice* h, uint32_t* host_out);
  * of site (x, y); padding bits are 0.  2 * L * ceil(L/64) words.  Synchronises. */
 int sw_read_bonds(sw_lattice* h, uint64_t* host_out);
 
+/* Comparison only (no sweep uses it): the labelling scheme the paper builds
+ * on, iterated label equivalence (Sec. 2, the scan and analysis kernels
+ * repeated under a host loop until a scan changes no label), run on the
+ * active bonds of the last sweep.  dev_labels: caller-owned device buffer of
+ * N uint32 that receives label[i] = smallest site index of i's cluster (the
+ * same labels sw_read_labels gives); dev_flag: one caller-owned device uint32
+ * (scratch).  *iterations receives the number of scan + analysis passes,
+ * counting the last one, which changed nothing; *ms (if not NULL) the
+ * elapsed device time of the whole loop, host round trips included.  More
+ * than max_iter passes: SW_ECONVERGE.  Needs a sweep since init / load;
+ * synchronises the stream; leaves the lattice unchanged. */
+int sw_label_equivalence(sw_lattice* h, uint32_t* dev_labels, uint32_t* dev_flag, uint32_t max_iter,
+                         uint32_t* iterations, double* ms);
+
 /* Release the handle (not the workspace or the stream). */
 int sw_destroy(sw_lattice* h);
 

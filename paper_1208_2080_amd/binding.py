@@ -47,6 +47,8 @@ SIGNATURES = [
     ("sw_load_spins", ctypes.c_int, [_VP, _VP, _U32]),
     ("sw_read_labels", ctypes.c_int, [_VP, _VP]),
     ("sw_read_bonds", ctypes.c_int, [_VP, _VP]),
+    ("sw_label_equivalence", ctypes.c_int, [_VP, _VP, _VP, _U32, ctypes.POINTER(_U32),
+                                            ctypes.POINTER(ctypes.c_double)]),
     ("sw_destroy", ctypes.c_int, [_VP]),
     ("sw_batch_workspace_bytes", ctypes.c_int, [_PP, _U32, ctypes.POINTER(ctypes.c_size_t)]),
     ("sw_batch_init", ctypes.c_int, [_PP, _U32, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
@@ -197,6 +199,19 @@ class Lattice:
         out = np.empty((2, self.L, self.W), dtype=np.uint64)
         _check(lib().sw_read_bonds(self._h, out.ctypes.data_as(ctypes.c_void_p)))
         return out[0], out[1]
+
+    def label_equivalence(self, max_iter: int = 1 << 16):
+        """The paper's iterated label equivalence on the last sweep's bonds (a
+        comparison; no sweep uses it): (labels uint32 [L, L], passes, device ms)."""
+        labels = torch.empty(self.N, dtype=torch.int32, device=self.device)
+        flag = torch.zeros(1, dtype=torch.int32, device=self.device)
+        torch.cuda.current_stream(self.device).synchronize()   # buffers allocated before first use
+        it = ctypes.c_uint32()
+        ms = ctypes.c_double()
+        _check(lib().sw_label_equivalence(self._h, ctypes.c_void_p(labels.data_ptr()), ctypes.c_void_p(flag.data_ptr()),
+                                          int(max_iter), ctypes.byref(it), ctypes.byref(ms)))
+        out = labels.cpu().numpy().view(np.uint32).reshape(self.L, self.L)
+        return out, int(it.value), float(ms.value)
 
     def close(self):
         if self._h:

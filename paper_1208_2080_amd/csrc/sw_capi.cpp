@@ -434,6 +434,43 @@ int sw_read_bonds(sw_lattice* h, uint64_t* host_out)
     return SW_OK;
 }
 
+int sw_label_equivalence(sw_lattice* h, uint32_t* dev_labels, uint32_t* dev_flag, uint32_t max_iter,
+                         uint32_t* iterations, double* ms)
+{
+    if (!h || !dev_labels || !dev_flag || !iterations) return fail(SW_EINVAL, "NULL argument");
+    if (!h->have_sweep) return fail(SW_ESTATE, "no sweep since init / load");
+    if (max_iter == 0) return fail(SW_EINVAL, "max_iter must be >= 1");
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+    auto run = [&](uint32_t* it_out, float* ms_out) -> int {
+        HIP_TRY(hipEventRecord(ev[0], h->stream));
+        HIP_TRY(launch_le_init(h->d_desc, h->g.L, dev_labels, h->stream));
+        uint32_t it = 0, flag = 1;
+        // the host loop of the method: one scan + analysis pass, then read the flag
+        while (flag && it < max_iter) {
+            HIP_TRY(hipMemsetAsync(dev_flag, 0, sizeof(uint32_t), h->stream));
+            HIP_TRY(launch_le_iteration(h->d_desc, h->g.L, h->g.ty, dev_labels, dev_flag, h->stream));
+            HIP_TRY(hipMemcpyAsync(&flag, dev_flag, sizeof flag, hipMemcpyDeviceToHost, h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            ++it;
+        }
+        HIP_TRY(hipEventRecord(ev[1], h->stream));
+        HIP_TRY(hipEventSynchronize(ev[1]));
+        HIP_TRY(hipEventElapsedTime(ms_out, ev[0], ev[1]));
+        if (flag) return fail(SW_ECONVERGE, "label equivalence still changing after %u iterations", max_iter);
+        *it_out = it;
+        return SW_OK;
+    };
+    uint32_t it = 0;
+    float elapsed = 0.f;
+    int rc = run(&it, &elapsed);
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    if (rc) return rc;
+    *iterations = it;
+    if (ms) *ms = elapsed;
+    return check_device_error(h->desc, h->stream);
+}
+
 int sw_destroy(sw_lattice* h)
 {
     delete h;

@@ -29,4 +29,12 @@ hipError_t launch_init(const LatDesc* descs, uint32_t lat, size_t N, uint32_t ra
 hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, size_t N, hipStream_t s);
 hipError_t launch_bump(const LatDesc* descs, uint32_t count, const uint32_t* n_each, uint32_t n, hipStream_t s);
 
+// Iterated label equivalence over the bonds of descs[0]'s last sweep (a
+// comparison for the tile labeller; sw_ablation.hip): lab[i] = i, then one
+// scan + analysis pass per call of launch_le_iteration, which sets *flag when
+// the scan lowered a label.
+hipError_t launch_le_init(const LatDesc* descs, uint32_t L, uint32_t* lab, hipStream_t s);
+hipError_t launch_le_iteration(const LatDesc* descs, uint32_t L, uint32_t ty, uint32_t* lab, uint32_t* flag,
+                               hipStream_t s);
+
 }  // namespace swmi

@@ -1,0 +1,62 @@
+"""GPU: the paper's iterated label equivalence (kept as a comparison for the
+tile union-find) gives, on the same bonds, exactly the oracle's labels."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1208_2080_amd import binding
+from paper_1208_2080_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+CASES = [(64, 2, wl.critical_coupling(2), True),
+         (100, 3, wl.critical_coupling(3), True),
+         (2, 2, 1.5, True),
+         (129, 4, 0.9 * wl.critical_coupling(4), True),
+         (65, 5, 0.0, True),
+         (191, 2, float("inf"), False),
+         (320, 2, 1.2 * wl.critical_coupling(2), True)]
+
+
+@pytest.mark.parametrize("L,q,K,rs", CASES)
+def test_label_equivalence_matches_oracle_labels(L, q, K, rs):
+    say(f"label equivalence L={L} q={q} K={K}")
+    lat = binding.Lattice(L, q, K, seed=31, random_start=rs, obs_capacity=4)
+    ref = oracle.OracleLattice(L, q, K, 31, random_start=rs)
+    for t in range(3):
+        lat.sweep(1)
+        out = ref.sweep()
+        le, passes, ms = lat.label_equivalence()
+        assert np.array_equal(le, out["labels"]), f"sweep {t}"
+        assert passes >= 1 and ms > 0
+        if K == 0.0:
+            assert passes == 1   # no bond: the first scan already changes nothing
+        # the lattice itself is untouched
+        assert np.array_equal(lat.spins(), ref.s)
+        assert np.array_equal(lat.labels(), out["labels"])
+    lat.close()
+
+
+def test_label_equivalence_at_the_paper_size():
+    # q = 2 at K_c on 4096 x 4096 (Sec. 2 quotes the pass count there)
+    say("label equivalence L=4096")
+    lat = binding.Lattice(4096, 2, wl.critical_coupling(2), seed=5, obs_capacity=4)
+    lat.sweep(50)
+    counts = []
+    for _ in range(3):
+        lat.sweep(1)
+        le, passes, ms = lat.label_equivalence()
+        assert np.array_equal(le, lat.labels())
+        counts.append(passes)
+        say(f"  {passes} passes, {ms:.2f} ms")
+    assert min(counts) >= 2
+    lat.close()
