@@ -585,8 +585,23 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
             if (vs) lrow[x] = ga;
         }
     };
-    if (w == TX) parents_out(std::true_type{});
-    else parents_out(std::false_type{});
+    if (w == TX && r1 - r0 == RPW) {
+        // a full strip: all parent reads first, then all grandparent reads, so
+        // the LDS round trips overlap; the stores go out from the strip's
+        // (wave-uniform) base with 32-bit per-lane offsets
+        uint32_t p[RPW];
+#pragma unroll
+        for (uint32_t k = 0; k < RPW; ++k) p[k] = P[(r0 + k) * TX + x];
+#pragma unroll
+        for (uint32_t k = 0; k < RPW; ++k) p[k] = P[p[k]];
+        const gptr<char> strip = (gptr<char>)(glb(d.lab) + (size_t)(y0 + r0) * L + x0);
+#pragma unroll
+        for (uint32_t k = 0; k < RPW; ++k) *(gptr<uint32_t>)(strip + (k * L + x) * 4u) = global_index(p[k]);
+    } else if (w == TX) {
+        parents_out(std::true_type{});
+    } else {
+        parents_out(std::false_type{});
+    }
     // The tile's edges for the merge carry tile-local roots: lane i walks the
     // left and right sites of strip row i; the first and last strips walk the
     // top and bottom rows.
@@ -701,6 +716,14 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
 
     // Full tiles (the common case) need no masks for columns or rows outside;
     // a power-of-two L divides by a shift.
+    // The tile's entries are addressed from a wave-uniform base with 32-bit
+    // per-lane byte offsets (a tile spans fewer than 2^32 / 4 sites of the
+    // arrays), which keeps 64-bit address arithmetic out of the vector units.
+    const uint32_t site0 = wave * L + col;         // this lane's first site, from the tile origin
+    const uint32_t wave_step = NW * L;             // sites between a wave's consecutive rows
+    const gptr<const char> lab_tile = (gptr<const char>)(glb(d.lab) + (size_t)y0 * L + x0);
+    const gptr<char> s_tile = (gptr<char>)(glb(d.s) + (size_t)y0 * L + x0);
+
     auto body = [&](auto full, auto pow2) {
         constexpr bool FULL = decltype(full)::value;
         constexpr bool POW2 = decltype(pow2)::value;
@@ -709,7 +732,8 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
             const uint32_t r = wave + NW * j;
-            v[j] = (vcol && (FULL || r < h)) ? lab[(size_t)(y0 + r) * L + x0 + col] : 0u;
+            const uint32_t byte_off = (site0 + j * wave_step) * 4u;
+            v[j] = (vcol && (FULL || r < h)) ? *(gptr<const uint32_t>)(lab_tile + byte_off) : 0u;
         }
 
         uint32_t nterm = 0;   // wave-uniform
@@ -721,11 +745,22 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
             // site indices fit 32 bits (N <= 2^32) and rows, L fit 24 bits
             const uint32_t gi = __umul24(y0 + r, L) + x0 + col;
             const uint32_t vv = v[j];
-            // tile coordinates of the label (meaningless, and rejected, outside the tile)
-            const uint32_t vy = POW2 ? vv >> d.log2L : div_L(d, vv);
-            const uint32_t dy = vy - y0, dx = (POW2 ? (vv & (L - 1u)) : vv - __umul24(vy, L)) - x0;
-            const bool term = vcol && (vv == gi || dy >= (FULL ? TY : h) || dx >= (FULL ? TX : w));
-            if (vcol) E[li] = term ? vv : dy * TX + dx;
+            bool term;
+            uint32_t local;
+            if (FULL && POW2) {
+                // power-of-two L, aligned full tile: the label is inside iff it
+                // agrees with the site's own index outside the in-tile bits
+                const uint32_t inner = ((uint32_t)(TY - 1) << d.log2L) | (TX - 1u);
+                term = vv == gi || ((vv ^ gi) & ~inner) != 0u;
+                local = (((vv >> d.log2L) & (TY - 1u)) * TX) | (vv & (TX - 1u));
+            } else {
+                // tile coordinates of the label (meaningless, and rejected, outside the tile)
+                const uint32_t vy = POW2 ? vv >> d.log2L : div_L(d, vv);
+                const uint32_t dy = vy - y0, dx = (POW2 ? (vv & (L - 1u)) : vv - __umul24(vy, L)) - x0;
+                term = vcol && (vv == gi || dy >= (FULL ? TY : h) || dx >= (FULL ? TX : w));
+                local = dy * TX + dx;
+            }
+            if (vcol) E[li] = term ? vv : local;
             const uint64_t m = ballot(term);
             // terminals append to the list, the other lanes write their scratch slot
             const uint32_t at_list = nterm + lanes_below(m), at_scratch = PER * TX + lane;
@@ -769,7 +804,7 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
             const uint32_t r = wave + NW * j;
-            if (vcol && (FULL || r < h)) glb(d.s)[(size_t)(y0 + r) * L + x0 + col] = (uint8_t)e[j];
+            if (vcol && (FULL || r < h)) *(gptr<uint8_t>)(s_tile + (site0 + j * wave_step)) = (uint8_t)e[j];
         }
     };
     if (w == TX && h == TY) {
