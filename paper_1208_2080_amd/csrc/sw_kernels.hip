@@ -736,14 +736,17 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
             v[j] = (vcol && (FULL || r < h)) ? *(gptr<const uint32_t>)(lab_tile + byte_off) : 0u;
         }
 
+        // row j of this wave: tile index li0 + j NW TX, site index gi0 + j wave_step
+        // (site indices fit 32 bits, N <= 2^32; rows and L fit 24 bits)
+        const uint32_t li0 = wave * TX + col;
+        const uint32_t gi0 = __umul24(y0 + wave, L) + x0 + col;
         uint32_t nterm = 0;   // wave-uniform
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
             const uint32_t r = wave + NW * j;
             if (!FULL && r >= h) continue;
-            const uint32_t li = r * TX + col;
-            // site indices fit 32 bits (N <= 2^32) and rows, L fit 24 bits
-            const uint32_t gi = __umul24(y0 + r, L) + x0 + col;
+            const uint32_t li = li0 + j * NW * TX;
+            const uint32_t gi = gi0 + j * wave_step;
             const uint32_t vv = v[j];
             bool term;
             uint32_t local;
@@ -760,11 +763,12 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
                 term = vcol && (vv == gi || dy >= (FULL ? TY : h) || dx >= (FULL ? TX : w));
                 local = dy * TX + dx;
             }
-            if (vcol) E[li] = term ? vv : local;
             const uint64_t m = ballot(term);
+            const bool is_term = lane_in(m);
+            if (vcol) E[li] = is_term ? vv : local;
             // terminals append to the list, the other lanes write their scratch slot
             const uint32_t at_list = nterm + lanes_below(m), at_scratch = PER * TX + lane;
-            my_list[term ? at_list : at_scratch] = (uint16_t)li;
+            my_list[is_term ? at_list : at_scratch] = (uint16_t)li;
             nterm = __builtin_amdgcn_readfirstlane(nterm + popc64(m));
         }
 
@@ -792,13 +796,13 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
             const uint32_t r = wave + NW * j;
             e[j] = TERM;
             if (vcol && (FULL || r < h)) {
-                uint32_t cur = r * TX + col, v = E[cur];
-                while (!(v & TERM) && v < cur) {
-                    cur = v;
-                    v = E[cur];
+                uint32_t cur = li0 + j * NW * TX, x = E[cur];
+                while (!(x & TERM) && x < cur) {
+                    cur = x;
+                    x = E[cur];
                 }
-                bad |= !(v & TERM);
-                e[j] = v;
+                bad |= !(x & TERM);
+                e[j] = x;
             }
         }
 #pragma unroll
