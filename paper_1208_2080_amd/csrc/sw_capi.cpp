@@ -327,8 +327,9 @@ int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms)
     if (n_sweeps > (1u << 20)) return fail(SW_EINVAL, "profile at most 2^20 sweeps per call");
     std::vector<hipEvent_t> ev(3 * (size_t)n_sweeps + 2, nullptr);
     int rc = SW_OK;
+    // timing-only events: no system-scope fence (cache write-back) at each one
     for (auto& e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
             rc = fail(SW_EHIP, "hipEventCreate failed");
             break;
         }
