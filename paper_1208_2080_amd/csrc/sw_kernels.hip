@@ -53,18 +53,23 @@ __device__ __forceinline__ TileGeom tile_geom(const LatDesc& d, uint32_t tile, u
     return g;
 }
 
-// Which lattice and tile this workgroup (or wave) works on.  Without a map the
-// work is the tiles of lattice 0, optionally spread over XCDs.
+// Which lattice (lat) and tile this workgroup (or wave) works on.  Without a
+// map the work is the tiles of lattice 0, optionally spread over the XCDs so
+// that each gets a contiguous band of tiles.  Mapped work (many lattices of
+// uneven cost) keeps the hardware's round-robin dealing, which balances the
+// XCDs better than bands do.
 __device__ __forceinline__ bool pick(const LatDesc* descs, const WorkItem* map, uint32_t idx,
-                                     bool spread, LatDesc& d, uint32_t& tile)
+                                     bool spread, LatDesc& d, uint32_t& tile, uint32_t& lat)
 {
     if (map) {
         const WorkItem it = map[idx];
         if (it.lat == INVALID) return false;
         d = descs[it.lat];
         tile = it.tile;
+        lat = it.lat;
         return true;
     }
+    lat = 0;
     d = descs[0];
     if (idx >= d.ntiles) return false;
     tile = spread ? xcd_tile(idx, d.ntiles) : idx;
@@ -391,8 +396,8 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
     __shared__ uint32_t tot[2];
 
     LatDesc d;
-    uint32_t tile;
-    if (!pick(descs, map, blockIdx.x, true, d, tile)) return;
+    uint32_t tile, lat;
+    if (!pick(descs, map, blockIdx.x, true, d, tile, lat)) return;
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t t = *glb(d.counter) + k;
     const bool meas = d.cap != 0;
@@ -635,8 +640,8 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
     const uint32_t idx = blockIdx.x * 4 + wave;
     if (idx >= nitems) return;
     LatDesc d;
-    uint32_t tile;
-    if (!pick(descs, map, idx, false, d, tile)) return;
+    uint32_t tile, lat;
+    if (!pick(descs, map, idx, false, d, tile, lat)) return;
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t EW = edge_words(TY);
     const uint64_t N = (uint64_t)d.L * d.L;
@@ -703,8 +708,8 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
     __shared__ uint16_t list[NW][PER * TX + 64];   // + a scratch slot per lane
 
     LatDesc d;
-    uint32_t tile;
-    if (!pick(descs, map, blockIdx.x, true, d, tile)) return;
+    uint32_t tile, lat;
+    if (!pick(descs, map, blockIdx.x, true, d, tile, lat)) return;
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t t = *glb(d.counter) + k;
     const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
@@ -839,11 +844,11 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_measure(const LatDesc* des
     __shared__ uint32_t hist[256];
     __shared__ uint32_t tot;
     LatDesc d;
-    uint32_t tile;
-    if (!pick(descs, map, blockIdx.x, true, d, tile)) return;
+    uint32_t tile, lat;
+    if (!pick(descs, map, blockIdx.x, true, d, tile, lat)) return;
     if (d.cap == 0) return;
     if (n_each) {
-        const uint32_t nl = n_each[map[blockIdx.x].lat];
+        const uint32_t nl = n_each[lat];
         if (nl == 0) return;
         k = nl - 1;
     }
