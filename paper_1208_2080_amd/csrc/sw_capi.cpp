@@ -90,7 +90,7 @@ inline uint32_t ring_slots(const Geometry& g) { return g.cap ? g.cap + 1 : 0; }
 
 // Byte offsets of one lattice's arrays inside its slice of the workspace.
 struct Carve {
-    size_t state, desc, spins, lab, bonds, edges, ring, total;
+    size_t state, desc, spins, lab, bonds, edges, ring, obs, total;
 };
 
 Carve carve(const Geometry& g)
@@ -109,6 +109,7 @@ Carve carve(const Geometry& g)
     c.bonds = take((size_t)g.ntiles * 2 * g.ty * 8);
     c.edges = take((size_t)g.ntiles * edge_words(g.ty) * 4);
     c.ring = take((size_t)ring_slots(g) * NCOPY * ring_stride(g.q) * 8);
+    c.obs = take((size_t)ring_slots(g) * (g.q + 1) * 8);
     c.total = off;
     return c;
 }
@@ -142,6 +143,7 @@ LatDesc make_desc(const Geometry& g, const sw_params* p, char* base, const Carve
     d.bonds = reinterpret_cast<uint64_t*>(base + c.bonds);
     d.edges = reinterpret_cast<uint32_t*>(base + c.edges);
     d.ring = g.cap ? reinterpret_cast<int64_t*>(base + c.ring) : nullptr;
+    d.obs = g.cap ? reinterpret_cast<int64_t*>(base + c.obs) : nullptr;
     d.counter = &st->counter;
     d.err = &st->err;
     d.L = g.L;
@@ -189,34 +191,29 @@ int check_device_error(const LatDesc& d, hipStream_t s)
     return SW_OK;
 }
 
-// Sum the NCOPY partial copies of ring records [first, first+n) into rows of
-// (2 + q) int64: n_unsat, n_active, n_0..n_{q-1}.  The records are copied in at
-// most two contiguous pieces (the ring may wrap) and one synchronisation.
+// Rows of (2 + q) int64 for ring records [first, first+n): n_unsat, n_active,
+// n_0..n_{q-1}.  A small kernel sums each record's NCOPY partial copies into
+// the lattice's staging area, so only (q + 1) words per sweep cross to the
+// host, in one copy and one synchronisation; n_0 = N - the other counts.
 int read_ring(const LatDesc& d, size_t N, hipStream_t s, uint32_t first, uint32_t n, int64_t* out)
 {
     if (n == 0) return SW_OK;
-    // Whole records in at most two contiguous copies (a strided copy of only
-    // the used words would move fewer bytes but in many tiny pieces).
-    const size_t R = ring_stride(d.q), rec = (size_t)NCOPY * R;
-    std::vector<int64_t> buf((size_t)n * rec);
-    const uint32_t slot0 = first % d.cap;
-    const uint32_t n1 = std::min<uint32_t>(n, d.cap - slot0);
-    HIP_TRY(hipMemcpyAsync(buf.data(), d.ring + (size_t)slot0 * rec, (size_t)n1 * rec * 8, hipMemcpyDeviceToHost, s));
-    if (n1 < n)
-        HIP_TRY(hipMemcpyAsync(buf.data() + (size_t)n1 * rec, d.ring, (size_t)(n - n1) * rec * 8,
-                               hipMemcpyDeviceToHost, s));
+    if (n >= d.cap) return fail(SW_ESTATE, "internal: %u records exceed the ring", n);
+    const uint32_t W = d.q + 1;
+    std::vector<int64_t> buf((size_t)n * W);
+    HIP_TRY(launch_ring_sum(d.ring, d.obs, d.cap, first % d.cap, n, d.q, s));
+    HIP_TRY(hipMemcpyAsync(buf.data(), d.obs, buf.size() * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (uint32_t k = 0; k < n; ++k) {
+        const int64_t* r = buf.data() + (size_t)k * W;
         int64_t* row = out + (size_t)k * (2 + d.q);
-        std::memset(row, 0, (2 + d.q) * 8);
-        for (uint32_t cpy = 0; cpy < NCOPY; ++cpy) {
-            const int64_t* r = buf.data() + (size_t)k * rec + (size_t)cpy * R;
-            row[0] += r[0];
-            row[1] += r[1];
-            for (uint32_t c = 1; c < d.q; ++c) row[2 + c] += r[1 + c];
-        }
+        row[0] = r[0];
+        row[1] = r[1];
         int64_t rest = 0;
-        for (uint32_t c = 1; c < d.q; ++c) rest += row[2 + c];
+        for (uint32_t c = 1; c < d.q; ++c) {
+            row[2 + c] = r[1 + c];
+            rest += r[1 + c];
+        }
         row[2] = (int64_t)N - rest;
     }
     return SW_OK;

@@ -919,6 +919,24 @@ __global__ __launch_bounds__(256) void k_resolve(const LatDesc* descs, uint32_t 
     }
 }
 
+// One thread per (record, word): the sum of the word over the record's NCOPY
+// partial copies.
+__global__ __launch_bounds__(256) void k_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, uint32_t slot0,
+                                                  uint32_t n, uint32_t q)
+{
+    const uint32_t W = q + 1;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * W) return;
+    const uint32_t rec = i / W, w = i - rec * W;
+    const uint32_t slot = (uint32_t)(((uint64_t)slot0 + rec) % slots);
+    const size_t R = ring_stride(q);
+    const gptr<const int64_t> base = glb(ring) + (size_t)slot * NCOPY * R + w;
+    int64_t sum = 0;
+#pragma unroll 8
+    for (uint32_t c = 0; c < NCOPY; ++c) sum += base[(size_t)c * R];
+    glb(out)[i] = sum;
+}
+
 // Advance sweep counters: lattice i by n (or by n_each[i] when given).
 __global__ void k_bump(const LatDesc* descs, uint32_t count, const uint32_t* n_each, uint32_t n)
 {
@@ -995,6 +1013,16 @@ hipError_t launch_init(const LatDesc* descs, uint32_t lat, size_t N, uint32_t ra
 hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, size_t N, hipStream_t s)
 {
     hipLaunchKernelGGL(k_resolve, dim3(init_grid(N)), dim3(256), 0, s, descs, lat);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, uint32_t slot0, uint32_t n, uint32_t q,
+                           hipStream_t s)
+{
+    const uint64_t total = (uint64_t)n * (q + 1);
+    if (total == 0) return hipSuccess;
+    if (total > 0xFFFFFFFFull || slot0 >= slots || n >= slots) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ring_sum, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, ring, out, slots, slot0, n, q);
     return hipGetLastError();
 }
 

@@ -13,6 +13,8 @@
 //                             n_active, n_1..n_{q-1} (n_0 = N - the rest);
 //                             NCOPY partial copies, each on cache lines of its
 //                             own, spread the workgroups' atomics
+//   obs     int64  [slots][q + 1]  staging for reads: the NCOPY partial copies of
+//                             the records being read, summed on the device
 //   state   DevState          sweep counter and error flag
 // Tiles are TX = 64 columns by TY rows (TY = 32, 64 or 128), numbered row-major.
 #pragma once
@@ -52,6 +54,7 @@ struct LatDesc {
     uint64_t* bonds;
     uint32_t* edges;
     int64_t* ring;
+    int64_t* obs;          // staging of summed ring records (reads only)
     uint32_t* counter;     // sweeps done
     uint32_t* err;         // -> DevState::err
     uint32_t L, q, W;
