@@ -157,3 +157,25 @@ def test_errors_surface_as_codes():
     with pytest.raises(binding.SwError) as e:
         lat.measure(0, 3)
     assert e.value.code == binding.SW_ESTATE
+
+
+def test_corrupted_label_forest_is_reported_not_walked():
+    # A label that points at a larger site breaks the forest invariant; the
+    # resolving walk must stop and report SW_ECONVERGE (every walk steps only to
+    # smaller indices, so it ends).  The corruption is written from the host
+    # into the workspace, between two calls.
+    L = 16
+    lat = binding.Lattice(L, 2, wl.critical_coupling(2), seed=3, obs_capacity=4)
+    lat.sweep(1)
+    good = lat.labels()                      # resolves the forest in place
+    # the labels follow the state (256 B), the descriptor (one 256-byte block)
+    # and the spins (L*L bytes, 256-aligned) in the workspace
+    off = 256 + 256 + ((L * L + 255) // 256) * 256
+    words = lat.ws[off:off + 4 * L * L].view(torch.int32)
+    assert np.array_equal(words.cpu().numpy().view(np.uint32).reshape(L, L), good)
+    words[5] = L * L - 1                     # site 5 now points above itself
+    torch.cuda.synchronize()
+    with pytest.raises(binding.SwError) as e:
+        lat.labels()
+    assert e.value.code == binding.SW_ECONVERGE
+    lat.close()
