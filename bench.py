@@ -266,7 +266,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u8",
+        "dtype": "u32",   # 32-bit integer arithmetic (draws, thresholds, labels); spins stored as u8
         "data": "synthetic",
         "config": {"workload": f"SW sweep, 2D Potts L={L} q={q} K={K:.9f} periodic, "
                                f"{'random' if cfg['random_start'] else 'cold'} start, "
