@@ -382,6 +382,7 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
 {
     constexpr uint32_t NW = waves_of<TY>(), NT = threads_of<TY>();
     constexpr uint32_t RPW = TY / NW;  // rows per wave (even)
+    static_assert(RPW < 32, "per-lane measurement counters hold at most 31 rows");
     constexpr uint32_t QCAP = qcap_of<TY>();
     __shared__ uint32_t P[TY * TX];    // union-find over the tile's sites
     __shared__ __align__(16) uint8_t sp[(TY + 1) * SPW];
@@ -423,8 +424,10 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
     // measurement: equal-spin pairs counted per wave (scalar), q = 2 spins
     // summed per lane (column), active bonds counted from the bond words
     uint32_t n_eq = 0, ones = 0;
-    const bool q4 = !q2 && d.q <= 4;   // states 1..3 counted per wave in scalars
-    uint32_t c1 = 0, c2 = 0, c3 = 0;
+    // q <= 8: each lane counts its sites in states 1..q-1 in the bytes of one
+    // 64-bit word (at most 16 rows per lane, so no byte overflows)
+    const bool q8 = !q2 && d.q <= 8;
+    uint64_t packed = 0;
     const uint32_t vbyte = vx ? 0xFFu : 0u;
     uint32_t lp = 0;
     const PhiloxKeys ks = philox_keys_v(d.key0, d.key1);
@@ -498,11 +501,10 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
         if (meas_prev) {
             n_eq += popc64(EX0) + popc64(EY0) + popc64(EX1) + popc64(EY1);   // EX1, EY1 are 0 without row r+1
             if (q2) ones += (s0 & vbyte) + (s1 & (two ? vbyte : 0u));
-            else if (q4) {
-                const uint64_t v1 = two ? validm : 0ull;
-                c1 += popc64(ballot(s0 == 1u) & validm) + popc64(ballot(s1 == 1u) & v1);
-                c2 += popc64(ballot(s0 == 2u) & validm) + popc64(ballot(s1 == 2u) & v1);
-                c3 += popc64(ballot(s0 == 3u) & validm) + popc64(ballot(s1 == 3u) & v1);
+            else if (q8) {
+                // (lanes outside the tile add nothing; their bytes may be stale)
+                packed += (uint64_t)vx << (8u * (s0 & 7u));
+                packed += (uint64_t)(vx && two) << (8u * (s1 & 7u));
             } else {
                 count_states(hist, d.q, lane, vx, s0);
                 if (two) count_states(hist, d.q, lane, vx, s1);
@@ -517,10 +519,11 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
             const uint32_t n1 = wave_sum_small<6>(ones);   // a lane counts at most TY / 4 <= 32 rows
             if (lane == 0 && n1) atomicAdd(&hist[1], n1);
         }
-        if (q4 && lane == 0) {
-            atomicAdd(&hist[1], c1);
-            atomicAdd(&hist[2], c2);
-            atomicAdd(&hist[3], c3);
+        if (q8) {
+            for (uint32_t c = 1; c < d.q; ++c) {
+                const uint32_t n = wave_sum_small<5>((uint32_t)(packed >> (8u * c)) & 0xFFu);
+                if (lane == 0 && n) atomicAdd(&hist[c], n);
+            }
         }
     }
     __syncthreads();
