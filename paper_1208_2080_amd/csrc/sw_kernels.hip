@@ -867,28 +867,25 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_measure(const LatDesc* des
     const bool vx = x < w;
     const uint64_t validm = (w == 64) ? ~0ull : ((1ull << w) - 1ull);
     const uint32_t r0 = wave * RPW, r1 = min(h, r0 + RPW);
-    // unequal pairs and states 1..3 counted per wave in scalars (q <= 4),
-    // other q through the shared histogram
-    const bool q4 = d.q <= 4;
-    uint32_t n_unsat = 0, c1 = 0, c2 = 0, c3 = 0;
+    static_assert(RPW < 32, "per-lane counters hold at most 31 rows");
+    // unequal pairs counted per wave in a scalar; for q <= 8 the states
+    // 1..q-1 in per-lane bytes of one word (as in k_bond_label), other q
+    // through the shared histogram
+    const bool q8 = d.q <= 8;
+    uint32_t n_unsat = 0;
+    uint64_t packed = 0;
     for (uint32_t r = r0; r < r1; ++r) {
         const uint8_t* row = sp + r * SPW;
         const uint32_t s = row[x], sr = row[x + 1], sd = row[SPW + x];
         n_unsat += popc64(ballot(s != sr) & validm) + popc64(ballot(s != sd) & validm);
-        if (q4) {
-            c1 += popc64(ballot(s == 1u) & validm);
-            c2 += popc64(ballot(s == 2u) & validm);
-            c3 += popc64(ballot(s == 3u) & validm);
-        } else {
-            count_states(hist, d.q, lane, vx, s);
-        }
+        if (q8) packed += (uint64_t)vx << (8u * (s & 7u));
+        else count_states(hist, d.q, lane, vx, s);
     }
-    if (lane == 0) {
-        atomicAdd(&tot, n_unsat);
-        if (q4) {
-            atomicAdd(&hist[1], c1);
-            atomicAdd(&hist[2], c2);
-            atomicAdd(&hist[3], c3);
+    if (lane == 0) atomicAdd(&tot, n_unsat);
+    if (q8) {
+        for (uint32_t c = 1; c < d.q; ++c) {
+            const uint32_t n = wave_sum_small<5>((uint32_t)(packed >> (8u * c)) & 0xFFu);
+            if (lane == 0 && n) atomicAdd(&hist[c], n);
         }
     }
     __syncthreads();
