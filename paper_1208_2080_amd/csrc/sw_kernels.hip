@@ -271,17 +271,34 @@ __device__ __forceinline__ void stage_spins(uint8_t* sp, const LatDesc& d, const
     }
 }
 
-// Count, for the measurement, the sites of one row in each state c >= 1.
-__device__ __forceinline__ void count_states(uint32_t* hist, uint32_t q, uint32_t lane, bool valid, uint32_t s)
+// Per-lane state counters of the measurement for q <= 16: byte (c & 7) of word
+// (c >> 3) counts this lane's sites in state c (at most 31 rows per lane).
+// q <= 8 needs only the first word (count_state_byte).
+__device__ __forceinline__ void count_state_byte(uint64_t (&w)[2], bool valid, uint32_t s)
 {
-    if (q <= 16) {
-        for (uint32_t c = 1; c < q; ++c) {
-            const uint32_t n = popc64(ballot(valid && s == c));
-            if (lane == 0 && n) atomicAdd(&hist[c], n);
-        }
-    } else if (valid && s) {
-        atomicAdd(&hist[s], 1u);
+    w[0] += (uint64_t)valid << (8u * (s & 7u));
+}
+
+__device__ __forceinline__ void count_state_bytes(uint64_t (&w)[2], bool valid, uint32_t s)
+{
+    const uint64_t one = (uint64_t)valid << (8u * (s & 7u));
+    w[0] += (s < 8u) ? one : 0ull;
+    w[1] += (s < 8u) ? 0ull : one;
+}
+
+// Wave totals of states 1..q-1 from the per-lane bytes, added into hist.
+__device__ __forceinline__ void flush_state_bytes(const uint64_t (&w)[2], uint32_t* hist, uint32_t q, uint32_t lane)
+{
+    for (uint32_t c = 1; c < q; ++c) {
+        const uint32_t n = wave_sum_small<5>((uint32_t)(w[c >> 3] >> (8u * (c & 7u))) & 0xFFu);
+        if (lane == 0 && n) atomicAdd(&hist[c], n);
     }
+}
+
+// Sites of one row in each state c >= 1 for q > 16, straight into hist.
+__device__ __forceinline__ void count_states(uint32_t* hist, bool valid, uint32_t s)
+{
+    if (valid && s) atomicAdd(&hist[s], 1u);
 }
 
 // Add a workgroup's measurement into a ring record (NCOPY partial copies).
@@ -424,93 +441,104 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
     // measurement: equal-spin pairs counted per wave (scalar), q = 2 spins
     // summed per lane (column), active bonds counted from the bond words
     uint32_t n_eq = 0, ones = 0;
-    // q <= 8: each lane counts its sites in states 1..q-1 in the bytes of one
-    // 64-bit word (at most 16 rows per lane, so no byte overflows)
-    const bool q8 = !q2 && d.q <= 8;
-    uint64_t packed = 0;
+    // q <= 16: each lane counts its sites in states 1..q-1 in the bytes of two
+    // 64-bit words (at most 16 rows per lane, so no byte overflows)
+    const bool q8 = !q2 && d.q <= 8, q16 = !q2 && d.q <= 16;
+    uint64_t packed[2] = {0ull, 0ull};
     const uint32_t vbyte = vx ? 0xFFu : 0u;
     uint32_t lp = 0;
     const PhiloxKeys ks = philox_keys_v(d.key0, d.key1);
     bool bad = false;   // this lane met a corrupted forest
     uint64_t hprev = 0, vprev = 0;
 
-    for (uint32_t r = r0; r < r1; r += 2) {
-        const bool two = r + 1 < r1;
-        if (uq.n > QCAP - 128) drain(uq, P, lane, bad);
-        const uint8_t* row = sp + r * SPW;
-        const uint32_t s0 = row[x], s0r = row[x + 1];
-        const uint32_t s1 = row[SPW + x], s1r = row[SPW + x + 1];
-        const uint32_t s2 = two ? row[2 * SPW + x] : 0u;
+    // The row loop, compiled twice: the q = 9..16 counters (two words per lane)
+    // stay out of the common instantiation, whose code they would otherwise
+    // perturb.
+    auto strip_rows = [&](auto wide) {
+        constexpr bool WIDE = decltype(wide)::value;
+        for (uint32_t r = r0; r < r1; r += 2) {
+            const bool two = r + 1 < r1;
+            if (uq.n > QCAP - 128) drain(uq, P, lane, bad);
+            const uint8_t* row = sp + r * SPW;
+            const uint32_t s0 = row[x], s0r = row[x + 1];
+            const uint32_t s1 = row[SPW + x], s1r = row[SPW + x + 1];
+            const uint32_t s2 = two ? row[2 * SPW + x] : 0u;
 
-        // Site indices in 32 bits: exact for every row of the lattice (N <= 2^32);
-        // a draw for row r+1 past the last row wraps but is never used.
-        const uint32_t base0 = (y0 + r) * L + x0;
-        uint32_t wx0, wy0, wx1, wy1;
-        if (even_L) {
-            const bool odd = x & 1u;
-            const uint32_t pair = ((odd ? base0 + L : base0) + (x & ~1u)) >> 1;
-            const u32x4 q4 = philox4x32_10(pair, 0u, t, 0u, ks);
-            const uint32_t recv0 = swap_pair(odd ? q4.x : q4.z);
-            const uint32_t recv1 = swap_pair(odd ? q4.y : q4.w);
-            wx0 = odd ? recv0 : q4.x;
-            wy0 = odd ? recv1 : q4.y;
-            wx1 = odd ? q4.z : recv0;
-            wy1 = odd ? q4.w : recv1;
-        } else {
-            const uint32_t ga = base0 + x, gb = base0 + L + x;
-            const u32x4 qa = philox4x32_10(ga >> 1, 0u, t, 0u, ks);
-            const u32x4 qb = philox4x32_10(gb >> 1, 0u, t, 0u, ks);
-            wx0 = (ga & 1u) ? qa.z : qa.x;
-            wy0 = (ga & 1u) ? qa.w : qa.y;
-            wx1 = (gb & 1u) ? qb.z : qb.x;
-            wy1 = (gb & 1u) ? qb.w : qb.y;
-        }
-        // equal-spin masks and draw masks as wave ballots; a bond needs both
-        const uint64_t EX0 = ballot(s0 == s0r) & validm, EY0 = ballot(s0 == s1) & validm;
-        const uint64_t BX0 = EX0 & ballot(wx0 <= d.thr_m1) & bondm;
-        const uint64_t BY0 = EY0 & ballot(wy0 <= d.thr_m1) & bondm;
-        uint64_t EX1 = 0, EY1 = 0, BX1 = 0, BY1 = 0;
-        if (two) {
-            EX1 = ballot(s1 == s1r) & validm;
-            EY1 = ballot(s1 == s2) & validm;
-            BX1 = EX1 & ballot(wx1 <= d.thr_m1) & bondm;
-            BY1 = EY1 & ballot(wy1 <= d.thr_m1) & bondm;
-        }
-        if (lane == 0) {
-            rb[r][0] = BX0;
-            rb[r][1] = BY0;
-            if (two) {
-                rb[r + 1][0] = BX1;
-                rb[r + 1][1] = BY1;
-            }
-        }
-
-        const uint64_t hx0 = BX0 & ~cross;
-        const uint32_t lab0 = row_labels(P, rl, uq, r, x, validm, hx0, vprev, hprev, lp);
-        lp = lab0;
-        hprev = hx0;
-        vprev = BY0;
-        if (two) {
-            const uint64_t hx1 = BX1 & ~cross;
-            const uint32_t lab1 = row_labels(P, rl, uq, r + 1, x, validm, hx1, vprev, hprev, lp);
-            lp = lab1;
-            hprev = hx1;
-            vprev = BY1;
-        }
-
-        if (meas_prev) {
-            n_eq += popc64(EX0) + popc64(EY0) + popc64(EX1) + popc64(EY1);   // EX1, EY1 are 0 without row r+1
-            if (q2) ones += (s0 & vbyte) + (s1 & (two ? vbyte : 0u));
-            else if (q8) {
-                // (lanes outside the tile add nothing; their bytes may be stale)
-                packed += (uint64_t)vx << (8u * (s0 & 7u));
-                packed += (uint64_t)(vx && two) << (8u * (s1 & 7u));
+            // Site indices in 32 bits: exact for every row of the lattice (N <= 2^32);
+            // a draw for row r+1 past the last row wraps but is never used.
+            const uint32_t base0 = (y0 + r) * L + x0;
+            uint32_t wx0, wy0, wx1, wy1;
+            if (even_L) {
+                const bool odd = x & 1u;
+                const uint32_t pair = ((odd ? base0 + L : base0) + (x & ~1u)) >> 1;
+                const u32x4 q4 = philox4x32_10(pair, 0u, t, 0u, ks);
+                const uint32_t recv0 = swap_pair(odd ? q4.x : q4.z);
+                const uint32_t recv1 = swap_pair(odd ? q4.y : q4.w);
+                wx0 = odd ? recv0 : q4.x;
+                wy0 = odd ? recv1 : q4.y;
+                wx1 = odd ? q4.z : recv0;
+                wy1 = odd ? q4.w : recv1;
             } else {
-                count_states(hist, d.q, lane, vx, s0);
-                if (two) count_states(hist, d.q, lane, vx, s1);
+                const uint32_t ga = base0 + x, gb = base0 + L + x;
+                const u32x4 qa = philox4x32_10(ga >> 1, 0u, t, 0u, ks);
+                const u32x4 qb = philox4x32_10(gb >> 1, 0u, t, 0u, ks);
+                wx0 = (ga & 1u) ? qa.z : qa.x;
+                wy0 = (ga & 1u) ? qa.w : qa.y;
+                wx1 = (gb & 1u) ? qb.z : qb.x;
+                wy1 = (gb & 1u) ? qb.w : qb.y;
+            }
+            // equal-spin masks and draw masks as wave ballots; a bond needs both
+            const uint64_t EX0 = ballot(s0 == s0r) & validm, EY0 = ballot(s0 == s1) & validm;
+            const uint64_t BX0 = EX0 & ballot(wx0 <= d.thr_m1) & bondm;
+            const uint64_t BY0 = EY0 & ballot(wy0 <= d.thr_m1) & bondm;
+            uint64_t EX1 = 0, EY1 = 0, BX1 = 0, BY1 = 0;
+            if (two) {
+                EX1 = ballot(s1 == s1r) & validm;
+                EY1 = ballot(s1 == s2) & validm;
+                BX1 = EX1 & ballot(wx1 <= d.thr_m1) & bondm;
+                BY1 = EY1 & ballot(wy1 <= d.thr_m1) & bondm;
+            }
+            if (lane == 0) {
+                rb[r][0] = BX0;
+                rb[r][1] = BY0;
+                if (two) {
+                    rb[r + 1][0] = BX1;
+                    rb[r + 1][1] = BY1;
+                }
+            }
+
+            const uint64_t hx0 = BX0 & ~cross;
+            const uint32_t lab0 = row_labels(P, rl, uq, r, x, validm, hx0, vprev, hprev, lp);
+            lp = lab0;
+            hprev = hx0;
+            vprev = BY0;
+            if (two) {
+                const uint64_t hx1 = BX1 & ~cross;
+                const uint32_t lab1 = row_labels(P, rl, uq, r + 1, x, validm, hx1, vprev, hprev, lp);
+                lp = lab1;
+                hprev = hx1;
+                vprev = BY1;
+            }
+
+            if (meas_prev) {
+                n_eq += popc64(EX0) + popc64(EY0) + popc64(EX1) + popc64(EY1);   // EX1, EY1 are 0 without row r+1
+                if (q2) ones += (s0 & vbyte) + (s1 & (two ? vbyte : 0u));
+                else if (q8) {
+                    // (lanes outside the tile add nothing; their bytes may be stale)
+                    count_state_byte(packed, vx, s0);
+                    count_state_byte(packed, vx && two, s1);
+                } else if (WIDE) {
+                    count_state_bytes(packed, vx, s0 & 15u);
+                    count_state_bytes(packed, vx && two, s1 & 15u);
+                } else {
+                    count_states(hist, vx, s0);
+                    if (two) count_states(hist, vx, s1);
+                }
             }
         }
-    }
+    };
+    if (q16 && !q8) strip_rows(std::true_type{});
+    else strip_rows(std::false_type{});
     seam[wave][lane] = lp;
     if (meas_prev) {
         // every site of the strip owns two bonds
@@ -519,12 +547,7 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
             const uint32_t n1 = wave_sum_small<6>(ones);   // a lane counts at most TY / 4 <= 32 rows
             if (lane == 0 && n1) atomicAdd(&hist[1], n1);
         }
-        if (q8) {
-            for (uint32_t c = 1; c < d.q; ++c) {
-                const uint32_t n = wave_sum_small<5>((uint32_t)(packed >> (8u * c)) & 0xFFu);
-                if (lane == 0 && n) atomicAdd(&hist[c], n);
-            }
-        }
+        if (q16) flush_state_bytes(packed, hist, d.q, lane);
     }
     __syncthreads();
 
@@ -868,26 +891,22 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_measure(const LatDesc* des
     const uint64_t validm = (w == 64) ? ~0ull : ((1ull << w) - 1ull);
     const uint32_t r0 = wave * RPW, r1 = min(h, r0 + RPW);
     static_assert(RPW < 32, "per-lane counters hold at most 31 rows");
-    // unequal pairs counted per wave in a scalar; for q <= 8 the states
-    // 1..q-1 in per-lane bytes of one word (as in k_bond_label), other q
-    // through the shared histogram
-    const bool q8 = d.q <= 8;
+    // unequal pairs counted per wave in a scalar; for q <= 16 the states
+    // 1..q-1 in per-lane bytes (as in k_bond_label), other q through the
+    // shared histogram
+    const bool q8 = d.q <= 8, q16 = d.q <= 16;
     uint32_t n_unsat = 0;
-    uint64_t packed = 0;
+    uint64_t packed[2] = {0ull, 0ull};
     for (uint32_t r = r0; r < r1; ++r) {
         const uint8_t* row = sp + r * SPW;
         const uint32_t s = row[x], sr = row[x + 1], sd = row[SPW + x];
         n_unsat += popc64(ballot(s != sr) & validm) + popc64(ballot(s != sd) & validm);
-        if (q8) packed += (uint64_t)vx << (8u * (s & 7u));
-        else count_states(hist, d.q, lane, vx, s);
+        if (q8) count_state_byte(packed, vx, s);
+        else if (q16) count_state_bytes(packed, vx, s & 15u);
+        else count_states(hist, vx, s);
     }
     if (lane == 0) atomicAdd(&tot, n_unsat);
-    if (q8) {
-        for (uint32_t c = 1; c < d.q; ++c) {
-            const uint32_t n = wave_sum_small<5>((uint32_t)(packed >> (8u * c)) & 0xFFu);
-            if (lane == 0 && n) atomicAdd(&hist[c], n);
-        }
-    }
+    if (q16) flush_state_bytes(packed, hist, d.q, lane);
     __syncthreads();
     int64_t* rp = ring_record(d, t, blockIdx.x % NCOPY);
     if (tid == 0) atomic_add_i64(&rp[0], tot);

@@ -75,7 +75,7 @@ def test_ragged_sizes(L):
     compare_sweeps(L, 2, wl.critical_coupling(2), seed=L, sweeps=8)
 
 
-@pytest.mark.parametrize("q", [3, 4, 7, 10, 17, 255])
+@pytest.mark.parametrize("q", [3, 4, 7, 8, 9, 10, 16, 17, 255])
 def test_many_states(q):
     compare_sweeps(96, q, wl.critical_coupling(q), seed=10 + q, sweeps=8)
     compare_sweeps(33, q, wl.critical_coupling(q), seed=20 + q, sweeps=5, random_start=False)
