@@ -1,5 +1,7 @@
 """GPU: the paper's iterated label equivalence (kept as a comparison for the
 tile union-find) gives, on the same bonds, exactly the oracle's labels."""
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -46,17 +48,26 @@ def test_label_equivalence_matches_oracle_labels(L, q, K, rs):
     lat.close()
 
 
+def paper_value(name):
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_values.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#") and line.split()[0] == name:
+                return float(line.split()[1])
+    raise KeyError(name)
+
+
 def test_label_equivalence_at_the_paper_size():
-    # q = 2 at K_c on 4096 x 4096 (Sec. 2 quotes the pass count there)
+    # q = 2 at K_c on 4096 x 4096, where Sec. 2 gives the mean pass count (about
+    # 8.6); the count of a racy scan varies by a pass or so from sweep to sweep
     say("label equivalence L=4096")
     lat = binding.Lattice(4096, 2, wl.critical_coupling(2), seed=5, obs_capacity=4)
     lat.sweep(50)
     counts = []
-    for _ in range(3):
+    for _ in range(5):
         lat.sweep(1)
         le, passes, ms = lat.label_equivalence()
         assert np.array_equal(le, lat.labels())
         counts.append(passes)
         say(f"  {passes} passes, {ms:.2f} ms")
-    assert min(counts) >= 2
+    assert abs(np.mean(counts) - paper_value("label_equivalence_passes_4096_q2")) <= 1.5
     lat.close()
