@@ -475,6 +475,26 @@ int sw_destroy(sw_lattice* h)
     return SW_OK;
 }
 
+int sw_derived(uint32_t L, uint32_t q, const int64_t* row, double* out)
+{
+    if (!row || !out) return fail(SW_EINVAL, "NULL argument");
+    if (L < 2 || L > 65536 || q < 2 || q > 255) return fail(SW_EINVAL, "L = %u or q = %u out of range", L, q);
+    const int64_t N = (int64_t)L * L;
+    int64_t total = 0, most = 0;
+    for (uint32_t c = 0; c < q; ++c) {
+        const int64_t n = row[2 + c];
+        if (n < 0 || n > N) return fail(SW_EINVAL, "count of state %u is %lld", c, (long long)n);
+        total += n;
+        most = std::max(most, n);
+    }
+    if (total != N) return fail(SW_EINVAL, "state counts add up to %lld, not N = %lld", (long long)total, (long long)N);
+    const double Nd = (double)N;
+    out[0] = (double)row[0] / Nd;                              // energy per site (units of J)
+    out[1] = ((double)q * ((double)most / Nd) - 1.0) / (double)(q - 1);   // Potts order parameter
+    out[2] = (q == 2) ? (double)(row[2] - row[3]) : 0.0;         // Ising magnetisation
+    return SW_OK;
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ batched
@@ -502,6 +522,9 @@ struct sw_batch {
     std::vector<uint32_t> map_order;  // replica order of the uploaded map
     std::map<uint32_t, hipGraphExec_t> graphs;   // sweep_all graphs by sweep count
 };
+
+// sweep_all graphs kept per batch (one per distinct sweep count)
+constexpr size_t MAX_GRAPHS = 8;
 
 namespace {
 
@@ -715,14 +738,19 @@ int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps)
     // the graph bakes in the work map of "every replica"; make sure it is the one uploaded
     std::vector<uint32_t> order(b->n);
     for (uint32_t r = 0; r < b->n; ++r) order[r] = r;
-    if (it == b->graphs.end() || b->map_order != order) {
+    if (b->map_order != order || b->h_map.empty()) {
         std::vector<uint32_t> prefix;
         int rc = upload_map(b, all.data(), 1, &prefix);
         if (rc) return rc;
-        b->h_n = all;
-        HIP_TRY(hipMemcpyAsync(b->d_n, b->h_n.data(), b->n * sizeof(uint32_t), hipMemcpyHostToDevice, b->stream));
     }
     if (it == b->graphs.end()) {
+        // a bounded cache: past MAX_GRAPHS sweep counts, drop the older graphs
+        // (after the stream has finished any launch of them)
+        if (b->graphs.size() >= MAX_GRAPHS) {
+            HIP_TRY(hipStreamSynchronize(b->stream));
+            for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+            b->graphs.clear();
+        }
         const uint32_t M = (uint32_t)b->total_tiles;
         hipGraph_t graph;
         HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
@@ -734,9 +762,11 @@ int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps)
                 rc = SW_EHIP;
         }
         if (rc == SW_OK) {
+            // the sweep count is a constant of the graph: the measurement of the
+            // last sweep and the counter bump read nothing the host may change
             const Work w{b->d_descs, b->d_map, M, b->ty, b->stream};
-            if (launch_measure_each(w, b->d_n) != hipSuccess ||
-                launch_bump(b->d_descs, b->n, b->d_n, 0, b->stream) != hipSuccess)
+            if (launch_measure(w, n_sweeps - 1) != hipSuccess ||
+                launch_bump(b->d_descs, b->n, nullptr, n_sweeps, b->stream) != hipSuccess)
                 rc = SW_EHIP;
         }
         const hipError_t ec = hipStreamEndCapture(b->stream, &graph);

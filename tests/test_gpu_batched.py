@@ -45,6 +45,35 @@ def test_batch_sweep_all_matches_oracle(ty):
     b.close()
 
 
+def test_batch_sweep_all_graph_reuse_matches_oracle():
+    """Cached graphs replayed after other sweep counts, after uneven sweeps and
+    past the graph cache's bound keep every replica on the oracle's chain."""
+    say("batch sweep_all graph reuse")
+    b = binding.Batch(MIX, obs_capacity=64)
+    refs = [oracle.OracleLattice(r["L"], r["q"], r["K"], r["seed"], r.get("random_start", True)) for r in MIX]
+
+    def check(n_each):
+        for r, (ref, n) in enumerate(zip(refs, n_each)):
+            rows = ref.run(n) if n else None
+            assert b.sweeps_done(r) == ref.t, f"replica {r}"
+            assert np.array_equal(b.spins(r), ref.s), f"replica {r} after {n_each}"
+            if n:
+                assert np.array_equal(b.measure(r, ref.t - n, n), rows), f"replica {r} after {n_each}"
+
+    plan = [("all", 4), ("all", 5), ("all", 4), ("each", [2] * len(MIX)), ("all", 4),
+            ("each", [1, 0, 3, 0, 2, 0, 1, 0]), ("all", 5)]
+    # more distinct counts than the cache keeps, then the first again
+    plan += [("all", n) for n in (1, 2, 3, 6, 7, 8, 9)] + [("all", 4)]
+    for kind, n in plan:
+        if kind == "all":
+            b.sweep_all(n)
+            check([n] * len(MIX))
+        else:
+            b.sweep(n)
+            check(n)
+    b.close()
+
+
 def test_autotuned_batch_matches_oracle():
     say("batch autotune")
     best, ms = binding.autotune(MIX, obs_capacity=32, sweeps=4)
