@@ -75,9 +75,14 @@ size_t sw_workspace_bytes(const sw_params* p);
  * probability of Sec. 2 step (1) as an integer test on a 32-bit draw). */
 int sw_threshold(const sw_params* p, uint64_t* thr);
 
-/* Carve the lattice out of dev_ws (device pointer, ws_bytes bytes) and write the
- * initial spins on hip_stream (a hipStream_t; NULL = default stream).  *out
- * receives a host-side handle owned by the library. */
+/* State of Sec. 2: the spins S_i of Eq. (1) (here 0..q-1) on the L x L torus.
+ * The paper does not say how a run starts; init = 0 sets every spin to 0,
+ * init = 1 draws each spin from its own counter (see the keying above).
+ * Carves the lattice out of dev_ws (device pointer, ws_bytes bytes, 256-byte
+ * aligned: SW_ESPACE otherwise) and writes the initial spins on hip_stream (a
+ * hipStream_t; NULL = default stream), then synchronises.  *out receives a
+ * host-side handle owned by the library (freed by sw_destroy).  Bad
+ * parameters: SW_EINVAL, and *out is NULL. */
 int sw_init(const sw_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, sw_lattice** out);
 
 /* Enqueue n_sweeps SW sweeps (Sec. 2 steps (1)-(3)) on the handle's stream,
@@ -104,20 +109,27 @@ int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms);
 /* Number of sweeps done since sw_init (the index of the next sweep). */
 int sw_sweeps_done(const sw_lattice* h, uint32_t* out);
 
-/* Current spins, N bytes row-major.  Synchronises the stream. */
+/* The spins S_i of Eq. (1) after the last sweep (states 0..q-1), N bytes
+ * row-major (i = y*L + x) into caller-owned host memory.  Synchronises the
+ * stream; a kernel that tripped a safety cap gives SW_ECONVERGE. */
 int sw_read_spins(sw_lattice* h, uint8_t* host_out);
 
-/* Replace the spins (N bytes, each < q) and set the sweep counter to `sweep`
- * (checkpoint / resume).  Observables before `sweep` are dropped. */
+/* Checkpoint / resume of the Markov chain of Sec. 2: replace the spins with
+ * host_in (N bytes row-major, each < q: SW_EINVAL otherwise, nothing changed)
+ * and set the sweep counter to `sweep`, so that the next sweep draws exactly
+ * what sweep number `sweep` of an uninterrupted run draws.  Observables before
+ * `sweep` are dropped.  Synchronises the stream. */
 int sw_load_spins(sw_lattice* h, const uint8_t* host_in, uint32_t sweep);
 
 /* Cluster labels of the last sweep: N uint32, label[i] = smallest site index
  * of i's cluster.  Needs at least one sweep since init / load.  Synchronises. */
 int sw_read_labels(sw_lattice* h, uint32_t* host_out);
 
-/* Active bonds of the last sweep as two bit planes (+x, then +y), each L rows
- * of ceil(L/64) uint64 words; bit (x mod 64) of word x/64 of row y is the bond
- * of site (x, y); padding bits are 0.  2 * L * ceil(L/64) words.  Synchronises. */
+/* The bonds activated in step (1) of the last sweep (Sec. 2) as two bit planes
+ * (+x, then +y), each L rows of ceil(L/64) uint64 words; bit (x mod 64) of
+ * word x/64 of row y is the bond of site (x, y); padding bits are 0.
+ * 2 * L * ceil(L/64) words of caller-owned host memory.  Needs a sweep since
+ * init / load (SW_ESTATE otherwise).  Synchronises. */
 int sw_read_bonds(sw_lattice* h, uint64_t* host_out);
 
 /* Comparison only (no sweep uses it): the labelling scheme the paper builds
@@ -139,24 +151,34 @@ int sw_destroy(sw_lattice* h);
 
 /* ---------------------------------------------------------------- batched
  * Many independent lattices ("replicas") of uneven L, q and K swept by the
- * same kernels in one launch per phase.  Replica r behaves bit for bit like a
- * plain lattice with params[r] (same random draws: nothing but the replica's
- * own seed and sweep index keys them). */
+ * same kernels in one launch per phase.  The paper sweeps one lattice at a
+ * time; a batch runs that same sweep (Sec. 2 steps (1)-(3)) on every replica.
+ * Replica r behaves bit for bit like a plain lattice with params[r] (same
+ * random draws: nothing but the replica's own seed and sweep index keys them).
+ * Same conventions as the plain calls: caller-owned workspace and stream,
+ * asynchronous sweeps, synchronising reads, negative SW_E* codes. */
 
-/* Device bytes for n replicas. */
+/* Device bytes for the n replicas params[0..n-1] (each checked as by
+ * sw_workspace_bytes; all must have the same tile_rows: SW_EINVAL). */
 int sw_batch_workspace_bytes(const sw_params* params, uint32_t n, size_t* bytes);
 
+/* As sw_init for every replica, in one workspace of sw_batch_workspace_bytes()
+ * bytes (256-byte aligned).  Synchronises the stream. */
 int sw_batch_init(const sw_params* params, uint32_t n, void* dev_ws, size_t ws_bytes,
                   void* hip_stream, sw_batch** out);
 
-/* Sweep replica r n_sweeps[r] times (0 = leave it alone); asynchronous. */
+/* Sweep replica r n_sweeps[r] times (0 = leave it alone); n_sweeps is n host
+ * uint32.  Asynchronous. */
 int sw_batch_sweep(sw_batch* b, const uint32_t* n_sweeps);
 
-/* Same sweep count for every replica (captured once per count as a HIP graph
- * and replayed; on the legacy NULL stream, which cannot be captured, the
- * kernels are launched directly). */
+/* Same sweep count for every replica, captured once per count as a HIP graph
+ * and replayed (a few counts are cached per batch; the count is a constant of
+ * its graph).  On the legacy NULL stream, which cannot be captured, the kernels
+ * are launched directly.  Asynchronous. */
 int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps);
 
+/* sw_measure, sw_read_spins, sw_sweeps_done and sw_destroy for one replica
+ * (replica >= n: SW_EINVAL). */
 int sw_batch_measure(sw_batch* b, uint32_t replica, uint32_t first, uint32_t n, int64_t* host_out);
 int sw_batch_read_spins(sw_batch* b, uint32_t replica, uint8_t* host_out);
 int sw_batch_sweeps_done(const sw_batch* b, uint32_t replica, uint32_t* out);
@@ -192,13 +214,29 @@ int sw_tile_count(const sw_params* p, uint32_t* tiles);
  * to max_tiles tiles in total. */
 int sw_group_workspace_bytes(uint32_t max_lattices, uint64_t max_tiles, size_t* bytes);
 
+/* A group (no paper counterpart: the sweep of Sec. 2 on many resident
+ * lattices at once) with its scratch in dev_ws (sw_group_workspace_bytes()
+ * bytes, 256-byte aligned, caller-owned) on hip_stream.  tile_rows: 0
+ * (default), 32, 64 or 128; members must match it. */
 int sw_group_init(uint32_t max_lattices, uint64_t max_tiles, uint32_t tile_rows, void* dev_ws, size_t ws_bytes,
                   void* hip_stream, sw_group** out);
 
-/* Sweep lats[i] n_sweeps[i] times (0 = leave it alone); asynchronous. */
+/* Sweep lats[i] n_sweeps[i] times (0 = leave it alone), i < n, every lattice
+ * at most once, bound to the group's stream; each is swept exactly as
+ * sw_sweep would (Sec. 2 steps (1)-(3)).  Asynchronous. */
 int sw_group_sweep(sw_group* g, sw_lattice* const* lats, const uint32_t* n_sweeps, uint32_t n);
 
+/* Release the group's handle (not its workspace, stream or lattices). */
 int sw_group_destroy(sw_group* g);
+
+/* Energy and order parameter of Sec. 4 ("energy and magnetization", measured
+ * after each sweep) in FP64 from one observable row of sw_measure for an
+ * L x L lattice with q states: out[0] = n_unsat / N (energy per site of
+ * Eq. (1) in units of J), out[1] = (q max_c n_c / N - 1) / (q - 1) (Potts
+ * order parameter), out[2] = n_0 - n_1 for q = 2 (Ising magnetisation; 0 for
+ * other q).  row: 2 + q host int64; out: 3 host doubles.  Bad L or q, or a row
+ * whose counts do not add up to N: SW_EINVAL. */
+int sw_derived(uint32_t L, uint32_t q, const int64_t* row, double* out);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* sw_last_error(void);

@@ -60,6 +60,8 @@ def lib():
         L.or_init.restype = ctypes.c_int
         L.or_observe.argtypes = [ctypes.c_uint32, ctypes.c_uint32, u8p, i64p]
         L.or_observe.restype = None
+        L.or_derived.argtypes = [ctypes.c_uint32, ctypes.c_uint32, u8p, ctypes.POINTER(ctypes.c_double)]
+        L.or_derived.restype = None
         L.or_label.argtypes = [ctypes.c_uint32, u8p, u8p, u32p]
         L.or_label.restype = None
         L.or_sweep.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64,
@@ -126,6 +128,19 @@ def observe(s: np.ndarray, q: int) -> np.ndarray:
     obs = np.zeros(2 + q, dtype=np.int64)
     lib().or_observe(L, q, _p(s.reshape(-1), ctypes.c_uint8), _p(obs, ctypes.c_int64))
     return obs
+
+
+def derived(s: np.ndarray, q: int) -> dict:
+    """Energy per site e, Potts order parameter m and (q = 2) magnetisation M of
+    a configuration, in FP64 straight from the spins."""
+    s = np.ascontiguousarray(s, dtype=np.uint8)
+    L = s.shape[0]
+    out = np.zeros(3, dtype=np.float64)
+    lib().or_derived(L, q, _p(s.reshape(-1), ctypes.c_uint8), _p(out, ctypes.c_double))
+    d = {"e": float(out[0]), "m": float(out[1])}
+    if q == 2:
+        d["M"] = float(out[2])
+    return d
 
 
 def label(bx: np.ndarray, by: np.ndarray) -> np.ndarray:

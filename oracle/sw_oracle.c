@@ -149,6 +149,41 @@ void or_observe(uint32_t L, uint32_t q, const uint8_t* s, int64_t* obs)
     obs[0] = unsat;
 }
 
+/* Derived observables of one configuration in FP64, straight from the spins
+ * (Sec. 4 measures the energy and the magnetisation; these are the readings of
+ * them): out[0] = energy per site, the number of unequal nearest-neighbour
+ * pairs of Eq. (1) over N; out[1] = Potts order parameter
+ * (q * max_c f_c - 1) / (q - 1), f_c the fraction of sites in state c;
+ * out[2] = Ising magnetisation sum_i (1 - 2 s_i) for q = 2 (0 otherwise). */
+void or_derived(uint32_t L, uint32_t q, const uint8_t* s, double* out)
+{
+    double N = (double)L * (double)L;
+    double e = 0.0, mag = 0.0;
+    double* frac = (double*)calloc(q, sizeof(double));
+    if (!frac) {
+        out[0] = out[1] = out[2] = NAN;
+        return;
+    }
+    for (uint32_t y = 0; y < L; ++y) {
+        uint32_t yd = (y + 1 == L) ? 0 : y + 1;
+        for (uint32_t x = 0; x < L; ++x) {
+            uint32_t xr = (x + 1 == L) ? 0 : x + 1;
+            uint8_t si = s[(uint64_t)y * L + x];
+            if (si != s[(uint64_t)y * L + xr]) e += 1.0;
+            if (si != s[(uint64_t)yd * L + x]) e += 1.0;
+            frac[si] += 1.0;
+            mag += (si == 0) ? 1.0 : -1.0;
+        }
+    }
+    double fmax = 0.0;
+    for (uint32_t c = 0; c < q; ++c)
+        if (frac[c] > fmax) fmax = frac[c];
+    free(frac);
+    out[0] = e / N;
+    out[1] = ((double)q * (fmax / N) - 1.0) / (double)(q - 1);
+    out[2] = (q == 2) ? mag : 0.0;
+}
+
 /* ------------------------------------------------- Hoshen-Kopelman labels */
 
 /* Proper label: follow label[label] until it points at itself (Sec. 2), then

@@ -65,6 +65,7 @@ SIGNATURES = [
     ("sw_group_init", ctypes.c_int, [_U32, ctypes.c_uint64, _U32, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
     ("sw_group_sweep", ctypes.c_int, [_VP, _VP, _VP, _U32]),
     ("sw_group_destroy", ctypes.c_int, [_VP]),
+    ("sw_derived", ctypes.c_int, [_U32, _U32, _VP, _VP]),
     ("sw_last_error", ctypes.c_char_p, []),
 ]
 
@@ -123,14 +124,17 @@ def _stream_handle(stream) -> int:
 
 
 def derived(row: np.ndarray, L: int, q: int) -> dict:
-    """Energy per site and order parameter from one int64 observable row
-    [n_unsat, n_active, n_0, ..., n_{q-1}] (host FP64)."""
-    N = float(L) * L
-    counts = row[2:2 + q].astype(np.float64)
-    out = {"e": float(row[0]) / N, "m": (q * counts.max() / N - 1.0) / (q - 1)}
+    """Energy per site e, Potts order parameter m and (q = 2) magnetisation M
+    from one int64 observable row [n_unsat, n_active, n_0, ..., n_{q-1}]
+    (computed in FP64 by the library's sw_derived)."""
+    r = np.ascontiguousarray(row, dtype=np.int64)
+    assert r.size == 2 + q
+    out = (ctypes.c_double * 3)()
+    _check(lib().sw_derived(int(L), int(q), r.ctypes.data_as(ctypes.c_void_p), out))
+    d = {"e": float(out[0]), "m": float(out[1])}
     if q == 2:
-        out["M"] = float(row[2] - row[3])
-    return out
+        d["M"] = float(out[2])
+    return d
 
 
 class Lattice:

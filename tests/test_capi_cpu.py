@@ -110,3 +110,30 @@ def test_autotune_rejects_bad_arguments_before_any_launch():
     assert call([32, 128], nbytes=need - 256) == binding.SW_ESPACE
     assert call([32, 128], ws=0x10001, nbytes=need) == binding.SW_ESPACE
     assert best.value == 7                                 # nothing written on failure
+
+
+@pytest.mark.parametrize("L,q", [(2, 2), (7, 2), (16, 3), (33, 8), (5, 255)])
+def test_derived_matches_oracle(L, q):
+    """sw_derived (host FP64 arithmetic of the library) on int64 rows of random
+    configurations against the oracle's values computed from the spins."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(L + 100 * q))
+    for _ in range(4):
+        s = rng.integers(0, q, (L, L), dtype=np.uint8)
+        row = oracle.observe(s, q)
+        got, ref = binding.derived(row, L, q), oracle.derived(s, q)
+        assert set(got) == set(ref)
+        for k in ref:
+            assert math.isclose(got[k], ref[k], rel_tol=1e-12, abs_tol=1e-300) or got[k] == ref[k]
+
+
+def test_derived_rejects_bad_rows():
+    import numpy as np
+    row = np.array([0, 0, 3, 1], dtype=np.int64)      # counts add up to 4 = N for L = 2
+    assert binding.derived(row, 2, 2)["M"] == 2.0
+    out = (ctypes.c_double * 3)()
+    for bad, L, q in [(np.array([0, 0, 3, 2], dtype=np.int64), 2, 2),
+                      (np.array([0, 0, 5, -1], dtype=np.int64), 2, 2),
+                      (row, 1, 2), (row, 65537, 2), (row, 2, 1), (row, 2, 256)]:
+        rc = binding.lib().sw_derived(L, q, bad.ctypes.data_as(ctypes.c_void_p), out)
+        assert rc == binding.SW_EINVAL, (bad, L, q)

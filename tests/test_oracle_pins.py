@@ -59,6 +59,107 @@ def test_philox_matches_rocrand(rocrand_philox):
     assert np.array_equal(ref, mine)
 
 
+def _bond_draws_ref(rocrand_philox, seed, sweep, sites):
+    """(wx, wy) of each site from rocRAND: counter (pair lo, pair hi, sweep, 0)
+    with pair = site >> 1; site parity b takes words 2b (+x) and 2b+1 (+y)."""
+    sites = [int(i) for i in sites]
+    rows = [[(i >> 1) & 0xFFFFFFFF, i >> 33, sweep, 0, seed & 0xFFFFFFFF, seed >> 32] for i in sites]
+    w = rocrand_philox(rows)
+    b = np.array([i & 1 for i in sites])
+    wx = w[np.arange(len(sites)), 2 * b]
+    wy = w[np.arange(len(sites)), 2 * b + 1]
+    return wx, wy
+
+
+def test_bond_draws_match_rocrand(rocrand_philox):
+    rng = np.random.Generator(np.random.PCG64(21))
+    n = 12000
+    seeds = rng.integers(0, 2**64, n, dtype=np.uint64)
+    sweeps = rng.integers(0, 2**32, n, dtype=np.uint64)
+    sites = rng.integers(0, 2**32, n, dtype=np.uint64).astype(object)
+    # sites near 2^32 (the last rows of L = 65536), past it, and both parities
+    special = [0, 1, 2, 3, 2**32 - 2, 2**32 - 1, 2**32, 2**32 + 1, 2**33 - 1, 2**33, 2**33 + 1, 2**40 + 5]
+    sites[:len(special)] = special
+    for k in range(len(special), 200):   # odd-L row straddles: last site of a row, first of the next
+        L = int(rng.integers(3, 65536)) | 1
+        y = int(rng.integers(0, L - 1))
+        sites[k] = y * L + L - 1 + (k & 1)
+    for seed in (int(seeds[0]), 1, 2**32 + 7):
+        wx, wy = _bond_draws_ref(rocrand_philox, seed, int(sweeps[0]), sites[:400])
+        got = np.array([oracle.bond_draws(seed, int(sweeps[0]), int(i)) for i in sites[:400]], dtype=np.uint64)
+        assert np.array_equal(got[:, 0], wx) and np.array_equal(got[:, 1], wy)
+    rows = [[(int(i) >> 1) & 0xFFFFFFFF, int(i) >> 33, int(t), 0, int(sd) & 0xFFFFFFFF, int(sd) >> 32]
+            for i, t, sd in zip(sites, sweeps, seeds)]
+    w = rocrand_philox(rows)
+    b = np.array([int(i) & 1 for i in sites])
+    got = np.array([oracle.bond_draws(int(sd), int(t), int(i)) for i, t, sd in zip(sites, sweeps, seeds)],
+                   dtype=np.uint64)
+    assert np.array_equal(got[:, 0], w[np.arange(n), 2 * b])
+    assert np.array_equal(got[:, 1], w[np.arange(n), 2 * b + 1])
+
+
+@pytest.mark.parametrize("L,q,seed", [(13, 2, 3), (16, 3, 9), (7, 4, 2**32 + 5)])
+def test_sweep_bonds_follow_rocrand_draws(rocrand_philox, L, q, seed):
+    """The bonds of whole sweeps: active iff the spins agree and rocRAND's draw
+    for that site and direction is below floor(2^32 (1 - e^-K))."""
+    K = wl.critical_coupling(q)
+    with mpmath.workdps(60):
+        thr = int(mpmath.floor(mpmath.ldexp(-mpmath.expm1(-mpmath.mpf(K)), 32)))
+    lat = oracle.OracleLattice(L, q, K, seed=seed)
+    for t in range(3):
+        s = lat.s.copy()
+        out = lat.sweep()
+        wx, wy = _bond_draws_ref(rocrand_philox, seed, t, range(L * L))
+        wx = wx.reshape(L, L)
+        wy = wy.reshape(L, L)
+        bx = (s == np.roll(s, -1, axis=1)) & (wx < thr)
+        by = (s == np.roll(s, -1, axis=0)) & (wy < thr)
+        assert np.array_equal(out["bx"].astype(bool), bx), f"sweep {t}"
+        assert np.array_equal(out["by"].astype(bool), by), f"sweep {t}"
+
+
+# ------------------------------------------------------ derived observables
+
+def _derived_brute(s, q):
+    L = s.shape[0]
+    e = 0
+    counts = [0] * q
+    for y in range(L):
+        for x in range(L):
+            v = int(s[y, x])
+            e += (v != int(s[y, (x + 1) % L])) + (v != int(s[(y + 1) % L, x]))
+            counts[v] += 1
+    N = L * L
+    out = {"e": e / N, "m": (q * max(counts) / N - 1) / (q - 1)}
+    if q == 2:
+        out["M"] = counts[0] - counts[1]
+    return out
+
+
+@pytest.mark.parametrize("L,q", [(2, 2), (5, 2), (6, 3), (9, 7), (4, 255)])
+def test_derived_brute_force(L, q):
+    rng = np.random.Generator(np.random.PCG64(L * 1000 + q))
+    for _ in range(5):
+        s = rng.integers(0, q, (L, L), dtype=np.uint8)
+        got, ref = oracle.derived(s, q), _derived_brute(s, q)
+        assert set(got) == set(ref)
+        for k in ref:
+            assert got[k] == pytest.approx(ref[k], rel=1e-15, abs=1e-15)
+
+
+def test_derived_closed_forms():
+    L = 8
+    cold = np.zeros((L, L), dtype=np.uint8)
+    assert oracle.derived(cold, 2) == {"e": 0.0, "m": 1.0, "M": float(L * L)}
+    assert oracle.derived(cold + 2, 5) == {"e": 0.0, "m": 1.0}
+    # checkerboard: every bond unequal, equal populations
+    assert oracle.derived(wl.checkerboard(L), 2) == {"e": 2.0, "m": 0.0, "M": 0.0}
+    # stripes of period q along x: every +x bond unequal, every +y bond equal
+    q = 4
+    stripes = np.tile(np.arange(L, dtype=np.uint8) % q, (L, 1))
+    assert oracle.derived(stripes, q) == {"e": 1.0, "m": 0.0}
+
+
 # --------------------------------------------------------------- threshold
 
 def _thr_exact(K):
