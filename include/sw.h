@@ -238,6 +238,35 @@ int sw_group_destroy(sw_group* g);
  * whose counts do not add up to N: SW_EINVAL. */
 int sw_derived(uint32_t L, uint32_t q, const int64_t* row, double* out);
 
+/* ------------------------------------------------- no-allocation variant
+ * For callers that cannot allocate device memory or set up a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  sw_sweep + sw_measure in one call that uses no workspace: the
+ * labels, bond words, edge records, observable ring, sweep counter and
+ * descriptor live in one fixed array of SW_STATIC_SCRATCH_BYTES of device
+ * memory that the library holds on every GPU it runs on until the process
+ * ends.  It calls no hipMalloc / hipFree and no allocating library routine,
+ * and enqueues only kernel launches, so it can be captured in a graph.
+ *
+ * p: L, q, K, seed, tile_rows as for sw_init (init and obs_capacity are
+ * checked as there but not used).  dev_spins: device, N bytes row-major,
+ * states < q (not checked), read and overwritten in place.  first_sweep:
+ * index of the first sweep (keys its draws exactly as sweep number
+ * first_sweep of a lattice made by sw_init).  dev_obs: device, n_sweeps rows
+ * of (2 + q) int64 as sw_measure gives them, or NULL for no measurement.
+ * dev_status: device uint32 that receives 0, or nonzero if a labelling safety
+ * cap tripped, or NULL.  Asynchronous on hip_stream; results are bit-identical
+ * to sw_init + sw_load_spins(spins, first_sweep) + sw_sweep + sw_measure.
+ * Errors: SW_EINVAL (parameters), SW_ESTATE (first_sweep + n_sweeps > 2^32-1),
+ * SW_ESPACE if the lattice needs more than SW_STATIC_SCRATCH_BYTES (about
+ * 4.3 bytes per site: L <= 2048 always fits), SW_EHIP.
+ * Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (other streams, other threads) race and give wrong results.  Each call
+ * clears what must start at zero (ring, counter, error flag) itself. */
+#define SW_STATIC_SCRATCH_BYTES (24u << 20)
+int sw_sweep_static(const sw_params* p, uint8_t* dev_spins, uint32_t first_sweep, uint32_t n_sweeps,
+                    int64_t* dev_obs, uint32_t* dev_status, void* hip_stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* sw_last_error(void);
 

@@ -66,6 +66,7 @@ SIGNATURES = [
     ("sw_group_sweep", ctypes.c_int, [_VP, _VP, _VP, _U32]),
     ("sw_group_destroy", ctypes.c_int, [_VP]),
     ("sw_derived", ctypes.c_int, [_U32, _U32, _VP, _VP]),
+    ("sw_sweep_static", ctypes.c_int, [_PP, _VP, _U32, _U32, _VP, _VP, _VP]),
     ("sw_last_error", ctypes.c_char_p, []),
 ]
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1036,3 +1037,127 @@ int sw_group_destroy(sw_group* g)
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------- no-allocation entry
+// For callers that cannot allocate (graph capture, tight serving loops): the
+// labels, bond words, edge records, ring, state and descriptor of one lattice
+// live in a fixed array of device memory that the library owns (one copy per
+// GPU, held until the process ends); the caller passes only the spins and the
+// observable rows.  Host code never uses the array's name as an address: the
+// device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) unsigned char scratch[SW_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, char*> g_scratch;   // device -> address of that device's copy of scratch
+
+int scratch_address(hipStream_t stream, char** out)
+{
+    int dev = 0;
+    if (stream) HIP_TRY(hipStreamGetDevice(stream, &dev));
+    else HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch.find(dev);
+    if (it == g_scratch.end()) {
+        int cur = 0;
+        HIP_TRY(hipGetDevice(&cur));
+        if (cur != dev) HIP_TRY(hipSetDevice(dev));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !ptr) return fail(SW_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        it = g_scratch.emplace(dev, static_cast<char*>(ptr)).first;
+    }
+    *out = it->second;
+    return SW_OK;
+}
+
+// Ring slots of the no-allocation form: a record is read out right after it
+// is complete, and the flip clears the slot after next ahead of time.
+constexpr uint32_t STATIC_SLOTS = 3;
+
+struct StaticCarve {
+    size_t state, desc, lab, bonds, edges, ring, total;
+};
+
+StaticCarve carve_static(const Geometry& g, bool measure)
+{
+    StaticCarve c{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    c.state = take(sizeof(DevState));
+    c.desc = take(sizeof(LatDesc));
+    c.lab = take(g.N * 4);
+    c.bonds = take((size_t)g.ntiles * 2 * g.ty * 8);
+    c.edges = take((size_t)g.ntiles * edge_words(g.ty) * 4);
+    c.ring = take(measure ? (size_t)STATIC_SLOTS * NCOPY * ring_stride(g.q) * 8 : 0);
+    c.total = off;
+    return c;
+}
+
+}  // namespace
+
+extern "C" int sw_sweep_static(const sw_params* p, uint8_t* dev_spins, uint32_t first_sweep, uint32_t n_sweeps,
+                               int64_t* dev_obs, uint32_t* dev_status, void* hip_stream)
+{
+    Geometry g;
+    int rc = check_params(p, &g);
+    if (rc) return rc;
+    if (!dev_spins) return fail(SW_EINVAL, "dev_spins is NULL");
+    if ((uint64_t)first_sweep + n_sweeps > 0xFFFFFFFFull) return fail(SW_ESTATE, "sweep counter would overflow");
+    const bool measure = dev_obs != nullptr;
+    const StaticCarve c = carve_static(g, measure);
+    if (c.total > SW_STATIC_SCRATCH_BYTES)
+        return fail(SW_ESPACE, "L = %u, tile_rows = %u needs %zu bytes of scratch; the library holds %u (L <= 2048 fits)",
+                    g.L, g.ty, c.total, (unsigned)SW_STATIC_SCRATCH_BYTES);
+    if (n_sweeps == 0) return SW_OK;
+    const hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    char* base = nullptr;
+    rc = scratch_address(stream, &base);
+    if (rc) return rc;
+
+    // the descriptor: the caller's spins, everything else in scratch
+    sw_params q = *p;
+    q.obs_capacity = measure ? STATIC_SLOTS - 1 : 0;
+    Carve pc{};
+    pc.state = c.state;
+    pc.desc = c.desc;
+    pc.lab = c.lab;
+    pc.bonds = c.bonds;
+    pc.edges = c.edges;
+    pc.ring = c.ring;
+    pc.obs = c.ring;   // no read staging in this form
+    Geometry gq = g;
+    gq.cap = q.obs_capacity;
+    LatDesc d = make_desc(gq, &q, base, pc);
+    if (!division_ok(g.L, d.magic, d.shift)) return fail(SW_EINVAL, "internal: division by L self-check failed");
+    d.s = dev_spins;
+    d.obs = nullptr;
+    DevState* st = reinterpret_cast<DevState*>(base + c.state);
+    LatDesc* d_desc = reinterpret_cast<LatDesc*>(base + c.desc);
+    int64_t* ring = measure ? reinterpret_cast<int64_t*>(base + c.ring) : nullptr;
+    const uint32_t ring_words = measure ? STATIC_SLOTS * NCOPY * ring_stride(g.q) : 0;
+    const uint32_t W = 2 + g.q;
+
+    HIP_TRY(launch_static_setup(d, d_desc, st, first_sweep, ring, ring_words, stream));
+    const Work w{d_desc, nullptr, g.ntiles, g.ty, stream};
+    for (uint32_t k = 0; k < n_sweeps; ++k) {
+        HIP_TRY(launch_bond_label(w, k, (measure && k > 0) ? 1u : 0u));
+        // the record of sweep k - 1 is complete once the bonds of sweep k are drawn
+        if (measure && k > 0)
+            HIP_TRY(launch_emit_row(ring, STATIC_SLOTS, first_sweep + k - 1, g.q, g.N, dev_obs + (size_t)(k - 1) * W,
+                                    nullptr, nullptr, stream));
+        HIP_TRY(launch_merge(w));
+        HIP_TRY(launch_flip(w, k));
+    }
+    if (measure) HIP_TRY(launch_measure(w, n_sweeps - 1));
+    if (measure || dev_status)
+        HIP_TRY(launch_emit_row(ring, STATIC_SLOTS, first_sweep + n_sweeps - 1, g.q, g.N,
+                                measure ? dev_obs + (size_t)(n_sweeps - 1) * W : nullptr, &st->err, dev_status, stream));
+    return SW_OK;
+}

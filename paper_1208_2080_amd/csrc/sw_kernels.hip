@@ -13,6 +13,7 @@
 // plus k_measure after the last sweep of a call, and small helpers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "sw_device.hpp"
@@ -966,6 +967,52 @@ __global__ void k_bump(const LatDesc* descs, uint32_t count, const uint32_t* n_e
     }
 }
 
+// Set-up of a lattice whose descriptor and state live in caller-independent
+// scratch (the no-allocation entry point): descriptor copied in, error flag
+// cleared, sweep counter set, ring records zeroed.  A plain kernel rather than
+// copies and fills, so the whole call can be captured in a graph.
+__global__ __launch_bounds__(256) void k_static_setup(LatDesc d, LatDesc* d_out, DevState* st, uint32_t counter,
+                                                      int64_t* ring, uint32_t ring_words)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        *d_out = d;
+        st->err = 0;
+        st->counter = counter;
+    }
+    for (uint32_t j = i; j < ring_words; j += gridDim.x * blockDim.x) glb(ring)[j] = 0;
+}
+
+// One finished ring record as an observable row [n_unsat, n_active, n_0, ...,
+// n_{q-1}] (n_0 = N minus the other counts), summed over its NCOPY partial
+// copies; optionally the error flag into *status.  One workgroup of 256.
+__global__ __launch_bounds__(256) void k_emit_row(const int64_t* ring, uint32_t slots, uint32_t slot, uint32_t q,
+                                                  uint64_t N, int64_t* row, const uint32_t* err, uint32_t* status)
+{
+    __shared__ int64_t word[256];
+    const uint32_t w = threadIdx.x;
+    if (row) {
+        const size_t R = ring_stride(q);
+        int64_t sum = 0;
+        if (w <= q) {
+            const gptr<const int64_t> base = glb(ring) + (size_t)(slot % slots) * NCOPY * R + w;
+            for (uint32_t c = 0; c < NCOPY; ++c) sum += base[(size_t)c * R];
+        }
+        word[w] = sum;
+        __syncthreads();
+        if (w == 0) {
+            int64_t rest = 0;
+            for (uint32_t c = 1; c < q; ++c) rest += word[1 + c];
+            glb(row)[0] = word[0];
+            glb(row)[1] = word[1];
+            glb(row)[2] = (int64_t)N - rest;
+        } else if (w < q) {
+            glb(row)[2 + w] = word[1 + w];
+        }
+    }
+    if (status && w == 0) *glb(status) = *glb(err);
+}
+
 // ---------------------------------------------------------------- launchers
 namespace {
 uint32_t init_grid(size_t N)
@@ -1042,6 +1089,22 @@ hipError_t launch_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, ui
     if (total == 0) return hipSuccess;
     if (total > 0xFFFFFFFFull || slot0 >= slots || n >= slots) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_ring_sum, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, ring, out, slots, slot0, n, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_static_setup(const LatDesc& d, LatDesc* d_out, DevState* st, uint32_t counter, int64_t* ring,
+                               uint32_t ring_words, hipStream_t s)
+{
+    const uint32_t grid = std::max(1u, std::min(1024u, (ring_words + 255) / 256));
+    hipLaunchKernelGGL(k_static_setup, dim3(grid), dim3(256), 0, s, d, d_out, st, counter, ring, ring_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_emit_row(const int64_t* ring, uint32_t slots, uint32_t slot, uint32_t q, uint64_t N, int64_t* row,
+                           const uint32_t* err, uint32_t* status, hipStream_t s)
+{
+    if (q < 2 || q > 255 || slots == 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_emit_row, dim3(1), dim3(256), 0, s, ring, slots, slot, q, N, row, err, status);
     return hipGetLastError();
 }
 

@@ -33,6 +33,17 @@ hipError_t launch_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, ui
                            hipStream_t s);
 hipError_t launch_bump(const LatDesc* descs, uint32_t count, const uint32_t* n_each, uint32_t n, hipStream_t s);
 
+// No-allocation entry point: copy the descriptor d to d_out, clear the error
+// flag, set the sweep counter and zero ring_words words of the ring (all in
+// caller-independent scratch).
+hipError_t launch_static_setup(const LatDesc& d, LatDesc* d_out, DevState* st, uint32_t counter, int64_t* ring,
+                               uint32_t ring_words, hipStream_t s);
+// Ring record `slot` (of `slots`) of a lattice with q states and N sites as one
+// observable row [n_unsat, n_active, n_0..n_{q-1}] at row (if row is not null);
+// *err copied to *status (if status is not null).
+hipError_t launch_emit_row(const int64_t* ring, uint32_t slots, uint32_t slot, uint32_t q, uint64_t N, int64_t* row,
+                           const uint32_t* err, uint32_t* status, hipStream_t s);
+
 // Iterated label equivalence over the bonds of descs[0]'s last sweep (a
 // comparison for the tile labeller; sw_ablation.hip): lab[i] = i, then one
 // scan + analysis pass per call of launch_le_iteration, which sets *flag when
