@@ -91,7 +91,7 @@ inline uint32_t ring_slots(const Geometry& g) { return g.cap ? g.cap + 1 : 0; }
 
 // Byte offsets of one lattice's arrays inside its slice of the workspace.
 struct Carve {
-    size_t state, desc, spins, lab, bonds, edges, ring, obs, total;
+    size_t state, desc, spins, lab, bonds, edges, nodes, ring, obs, total;
 };
 
 Carve carve(const Geometry& g)
@@ -109,6 +109,7 @@ Carve carve(const Geometry& g)
     c.lab = take(g.N * 4);
     c.bonds = take((size_t)g.ntiles * 2 * g.ty * 8);
     c.edges = take((size_t)g.ntiles * edge_words(g.ty) * 4);
+    c.nodes = take((size_t)g.ntiles * nslot(g.ty) * 8);
     c.ring = take((size_t)ring_slots(g) * NCOPY * ring_stride(g.q) * 8);
     c.obs = take((size_t)ring_slots(g) * (g.q + 1) * 8);
     c.total = off;
@@ -143,6 +144,7 @@ LatDesc make_desc(const Geometry& g, const sw_params* p, char* base, const Carve
     d.lab = reinterpret_cast<uint32_t*>(base + c.lab);
     d.bonds = reinterpret_cast<uint64_t*>(base + c.bonds);
     d.edges = reinterpret_cast<uint32_t*>(base + c.edges);
+    d.nodes = reinterpret_cast<uint64_t*>(base + c.nodes);
     d.ring = g.cap ? reinterpret_cast<int64_t*>(base + c.ring) : nullptr;
     d.obs = g.cap ? reinterpret_cast<int64_t*>(base + c.obs) : nullptr;
     d.counter = &st->counter;
@@ -179,6 +181,7 @@ struct sw_lattice {
     uint32_t done;           // sweeps done since init (index of the next sweep)
     uint32_t first_obs;      // first sweep whose observables exist
     bool have_sweep;         // labels and bonds of a sweep are in place
+    bool labels_resolved;    // the labels hold smallest site indices (after sw_read_labels)
 };
 
 namespace {
@@ -313,6 +316,7 @@ int sw_sweep(sw_lattice* h, uint32_t n_sweeps)
     if (rc) return rc;
     h->done += n_sweeps;
     h->have_sweep = true;
+    h->labels_resolved = false;
     return SW_OK;
 }
 
@@ -336,6 +340,7 @@ int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms)
     if (rc == SW_OK) {
         h->done += n_sweeps;
         h->have_sweep = true;
+        h->labels_resolved = false;
         if (hipEventSynchronize(ev.back()) != hipSuccess) rc = fail(SW_EHIP, "hipEventSynchronize failed");
     }
     for (uint32_t k = 0; rc == SW_OK && k < n_sweeps; ++k) {
@@ -401,6 +406,7 @@ int sw_load_spins(sw_lattice* h, const uint8_t* host_in, uint32_t sweep)
     h->done = sweep;
     h->first_obs = sweep;
     h->have_sweep = false;
+    h->labels_resolved = false;
     return SW_OK;
 }
 
@@ -408,7 +414,10 @@ int sw_read_labels(sw_lattice* h, uint32_t* host_out)
 {
     if (!h || !host_out) return fail(SW_EINVAL, "NULL argument");
     if (!h->have_sweep) return fail(SW_ESTATE, "no sweep since init / load");
-    HIP_TRY(launch_resolve(h->d_desc, 0, h->g.N, h->stream));
+    if (!h->labels_resolved) {
+        HIP_TRY(launch_resolve(h->d_desc, 0, h->g.ntiles, h->g.ty, h->stream));
+        h->labels_resolved = true;
+    }
     HIP_TRY(hipMemcpyAsync(host_out, h->desc.lab, h->g.N * 4, hipMemcpyDeviceToHost, h->stream));
     return check_device_error(h->desc, h->stream);
 }
@@ -1026,6 +1035,7 @@ int sw_group_sweep(sw_group* g, sw_lattice* const* lats, const uint32_t* n_sweep
         if (n_sweeps[i]) {
             lats[i]->done += n_sweeps[i];
             lats[i]->have_sweep = true;
+            lats[i]->labels_resolved = false;
         }
     return SW_OK;
 }
@@ -1078,7 +1088,7 @@ int scratch_address(hipStream_t stream, char** out)
 constexpr uint32_t STATIC_SLOTS = 3;
 
 struct StaticCarve {
-    size_t state, desc, lab, bonds, edges, ring, total;
+    size_t state, desc, lab, bonds, edges, nodes, ring, total;
 };
 
 StaticCarve carve_static(const Geometry& g, bool measure)
@@ -1095,6 +1105,7 @@ StaticCarve carve_static(const Geometry& g, bool measure)
     c.lab = take(g.N * 4);
     c.bonds = take((size_t)g.ntiles * 2 * g.ty * 8);
     c.edges = take((size_t)g.ntiles * edge_words(g.ty) * 4);
+    c.nodes = take((size_t)g.ntiles * nslot(g.ty) * 8);
     c.ring = take(measure ? (size_t)STATIC_SLOTS * NCOPY * ring_stride(g.q) * 8 : 0);
     c.total = off;
     return c;
@@ -1130,6 +1141,7 @@ extern "C" int sw_sweep_static(const sw_params* p, uint8_t* dev_spins, uint32_t 
     pc.lab = c.lab;
     pc.bonds = c.bonds;
     pc.edges = c.edges;
+    pc.nodes = c.nodes;
     pc.ring = c.ring;
     pc.obs = c.ring;   // no read staging in this form
     Geometry gq = g;

@@ -113,12 +113,15 @@ __device__ __forceinline__ uint32_t swap_pair(uint32_t v)
 }
 
 // ------------------------------------------------------- LDS union-find
-// P holds, for every site of the tile (tile-local index), a label that is never
-// larger than itself; roots point at themselves.  Entries only ever decrease
-// (unions hook the larger root under the smaller one with atomicMin; finds
-// point nodes at their grandparents), so every walk that steps only to
-// smaller indices ends.  A walk that stops at a node pointing to a larger
-// index has met a corrupted forest and sets `bad`, which the kernel reports.
+// P holds, for every site of the tile, a tile-local index (16 bits: a tile has
+// at most 2^13 sites) that is never larger than its own; roots point at
+// themselves.  Entries only ever decrease (unions hook the larger root under
+// the smaller one with a minimum; finds point nodes at their grandparents),
+// so every walk that steps only to smaller indices ends.  A walk that stops at
+// a node pointing to a larger index has met a corrupted forest and sets `bad`,
+// which the kernel reports.  16-bit entries halve the forest's LDS, so more
+// workgroups fit a CU; the minimum (there is no 16-bit LDS minimum) is a
+// compare-and-swap on the entry's 32-bit word.
 __device__ __forceinline__ uint32_t lds_ld(uint32_t* p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -127,11 +130,55 @@ __device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+__device__ __forceinline__ uint32_t lds_ld(uint16_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_st(uint16_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, (uint16_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Entry i of P set to `desired` if it holds `expect` (as a compare-and-swap
+// would); returns the entry's value before.  A failed 32-bit swap means the
+// word changed, so some lane made progress.
+__device__ __forceinline__ uint32_t lds_cas16(uint16_t* P, uint32_t i, uint32_t expect, uint32_t desired, bool& bad)
+{
+    uint32_t* const w = reinterpret_cast<uint32_t*>(P) + (i >> 1);
+    const uint32_t sh = (i & 1u) * 16u;
+    uint32_t cur = lds_ld(w);
+    for (uint32_t it = 0; it < LDS_CAP; ++it) {
+        const uint32_t old = (cur >> sh) & 0xFFFFu;
+        if (old != expect) return old;
+        const uint32_t seen = atomicCAS(w, cur, (cur & ~(0xFFFFu << sh)) | (desired << sh));
+        if (seen == cur) return old;
+        cur = seen;
+    }
+    bad = true;
+    return expect;
+}
+
+// min(P[i], v) into entry i; returns the entry's value before.
+__device__ __forceinline__ uint32_t lds_min16(uint16_t* P, uint32_t i, uint32_t v, bool& bad)
+{
+    uint32_t* const w = reinterpret_cast<uint32_t*>(P) + (i >> 1);
+    const uint32_t sh = (i & 1u) * 16u;
+    uint32_t cur = lds_ld(w);
+    for (uint32_t it = 0; it < LDS_CAP; ++it) {
+        const uint32_t old = (cur >> sh) & 0xFFFFu;
+        if (old <= v) return old;
+        const uint32_t seen = atomicCAS(w, cur, (cur & ~(0xFFFFu << sh)) | (v << sh));
+        if (seen == cur) return old;
+        cur = seen;
+    }
+    bad = true;
+    return v;
+}
 
 // Root of x while unions may still run, with path splitting: every visited
 // node is pointed at its grandparent (a stored value is always an ancestor,
 // so races with other finds and hooks are benign).
-__device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x, bool& bad)
+__device__ __forceinline__ uint32_t lds_find(uint16_t* P, uint32_t x, bool& bad)
 {
     uint32_t p = lds_ld(&P[x]);
     while (p < x) {
@@ -144,30 +191,14 @@ __device__ __forceinline__ uint32_t lds_find(uint32_t* P, uint32_t x, bool& bad)
     return x;
 }
 
-// Root of x once the forest no longer changes (no writes).  The first two
-// steps are taken without a branch (a root reads itself again), which covers
-// most sites; only deeper chains enter the loop.
-__device__ __forceinline__ uint32_t lds_root(const uint32_t* P, uint32_t x, bool& bad)
-{
-    uint32_t p = P[x];
-    x = min(p, x);
-    p = P[x];
-    while (p < x) {
-        x = p;
-        p = P[x];
-    }
-    bad |= p != x;
-    return x;
-}
-
-__device__ void lds_union(uint32_t* P, uint32_t a, uint32_t b, bool& bad)
+__device__ void lds_union(uint16_t* P, uint32_t a, uint32_t b, bool& bad)
 {
     for (uint32_t it = 0; it < LDS_CAP; ++it) {
         a = lds_find(P, a, bad);
         b = lds_find(P, b, bad);
         if (a == b) return;
         const uint32_t hi = max(a, b), lo = min(a, b);
-        const uint32_t old = __hip_atomic_fetch_min(&P[hi], lo, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const uint32_t old = lds_min16(P, hi, lo, bad);
         if (old == hi) return;
         // hi was hooked meanwhile: join its new parent with lo instead
         a = old;
@@ -176,60 +207,122 @@ __device__ void lds_union(uint32_t* P, uint32_t a, uint32_t b, bool& bad)
     bad = true;
 }
 
-// ---------------------------------------------------- global union-find
-// The finds read through the caches.  A stale value is a parent the node had
-// earlier, still a smaller index in the same cluster, so chases still end and
-// only ever reach true ancestors or stale roots; the hook itself is a
-// device-coherent atomicMin that returns the current parent, and a hook on a
-// stale root retries from that value.  Hence the forest stays exact.  As in
-// the LDS forest, walks step only to smaller indices (so they end and stay in
-// bounds) and a stop at a larger index sets `bad`.
+// ------------------------------------------------------ edge forest (global)
+// One node per tile-local cluster that touches a tile edge.  A node's word is
+// (key << 32) | parent: parent is a node id, key the smallest site index of the
+// parent (a root is its own parent, its key its own smallest site).  Words only
+// ever decrease, and ordering words orders keys, so hooking the root with the
+// larger word under the one with the smaller (a 64-bit atomicMin) leaves every
+// cluster's root at its smallest site.
+//
+// The finds read through the caches.  A stale word is one the node had
+// earlier, still pointing at an ancestor, so chases still end and only ever
+// reach true ancestors or stale roots; the hook itself is a device-coherent
+// atomicMin that returns the current word, and a hook on a stale root retries
+// from that value.  Every step goes to a strictly smaller key, so walks end
+// even in a corrupted forest; a step that does not (or leaves the node array)
+// sets `bad` and stops.
+__device__ __forceinline__ uint32_t node_of(uint64_t w) { return (uint32_t)w; }
+__device__ __forceinline__ uint32_t key_of(uint64_t w) { return (uint32_t)(w >> 32); }
 
-// Root of x with path splitting (every visited node is pointed at its
-// grandparent; any stored value is an ancestor, so races are benign).
-__device__ uint32_t g_find(gptr<uint32_t> lab, uint32_t x, bool& bad)
+__device__ __forceinline__ uint64_t min_coherent64(gptr<uint64_t> p, uint64_t v)
 {
-    uint32_t p = lab[x];
-    while (p < x) {
-        const uint32_t gp = lab[p];
-        if (gp < p) lab[x] = gp;   // only a real shortcut is worth a store
-        x = p;
-        p = gp;
-    }
-    bad |= p != x;
-    return x;
+    return __hip_atomic_fetch_min(reinterpret_cast<gptr<unsigned long long>>(p), (unsigned long long)v,
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ void g_unite(gptr<uint32_t> lab, uint64_t N, uint32_t a, uint32_t b, bool& bad)
+// Root word of node x whose word w was loaded already (x < n), with path
+// splitting (every visited node is pointed at its grandparent when that is a
+// real shortcut; any stored word is an ancestor's, so races are benign).
+// n: nodes in the array.
+__device__ uint64_t n_find_from(gptr<uint64_t> nodes, uint32_t n, uint32_t x, uint64_t w, bool& bad)
 {
-    if (a >= N || b >= N) {
-        bad = true;
-        return;
-    }
     for (uint32_t it = 0; it < UNITE_CAP; ++it) {
-        a = g_find(lab, a, bad);
-        b = g_find(lab, b, bad);
-        if (a == b) return;
-        const uint32_t hi = max(a, b), lo = min(a, b);
-        const uint32_t old = min_coherent(lab + hi, lo);
-        if (old == hi) return;
-        // hi was hooked meanwhile: join its new parent with lo instead
-        a = old;
-        b = lo;
+        const uint32_t p = node_of(w);
+        if (p == x) return w;
+        if (p >= n) break;
+        const uint64_t wp = nodes[p];
+        if (key_of(wp) >= key_of(w) && node_of(wp) != p) break;   // keys must fall
+        if (wp < w) nodes[x] = wp;
+        x = p;
+        w = wp;
+    }
+    bad = true;
+    return w;
+}
+
+// Read-only root search once the forest is final.
+__device__ uint64_t n_root(gptr<const uint64_t> nodes, uint32_t n, uint32_t x, bool& bad)
+{
+    if (x >= n) {
+        bad = true;
+        return 0;
+    }
+    uint64_t w = nodes[x];
+    for (uint32_t it = 0; it < UNITE_CAP; ++it) {
+        const uint32_t p = node_of(w);
+        if (p == x) return w;
+        if (p >= n) break;
+        const uint64_t wp = nodes[p];
+        if (key_of(wp) >= key_of(w) && node_of(wp) != p) break;
+        x = p;
+        w = wp;
+    }
+    bad = true;
+    return w;
+}
+
+// One step of a find (path splitting): from node x with word w to its parent.
+// Returns false (and sets bad) if the forest is corrupted.
+__device__ __forceinline__ bool n_step(gptr<uint64_t> nodes, uint32_t n, uint32_t& x, uint64_t& w, uint64_t wp,
+                                       bool& bad)
+{
+    const uint32_t p = node_of(w);
+    if (key_of(wp) >= key_of(w) && node_of(wp) != p) {   // keys must fall
+        bad = true;
+        return false;
+    }
+    if (wp < w) nodes[x] = wp;
+    x = p;
+    w = wp;
+    return true;
+}
+
+// Roots of nodes a and b (words wa, wb already loaded), both chains walked
+// together so that their loads overlap.  On return a, b are the root nodes
+// and wa, wb their words.
+__device__ void n_find2(gptr<uint64_t> nodes, uint32_t n, uint32_t& a, uint64_t& wa, uint32_t& b, uint64_t& wb,
+                        bool& bad)
+{
+    for (uint32_t it = 0; it < UNITE_CAP; ++it) {
+        const bool ra = node_of(wa) == a, rb = node_of(wb) == b;
+        if (ra && rb) return;
+        if (node_of(wa) >= n || node_of(wb) >= n) break;
+        const uint64_t wpa = ra ? wa : nodes[node_of(wa)];
+        const uint64_t wpb = rb ? wb : nodes[node_of(wb)];
+        if (!ra && !n_step(nodes, n, a, wa, wpa, bad)) return;
+        if (!rb && !n_step(nodes, n, b, wb, wpb, bad)) return;
     }
     bad = true;
 }
 
-// Read-only root search once the forest is final (after the merge kernel).
-__device__ uint32_t g_root(gptr<uint32_t> lab, uint32_t x, bool& bad)
+// Join the clusters of nodes a and b (a, b < n; words wa, wb already loaded).
+__device__ void n_unite(gptr<uint64_t> nodes, uint32_t n, uint32_t a, uint32_t b, uint64_t wa, uint64_t wb, bool& bad)
 {
-    uint32_t p = lab[x];
-    while (p < x) {
-        x = p;
-        p = lab[x];
+    for (uint32_t it = 0; it < UNITE_CAP; ++it) {
+        n_find2(nodes, n, a, wa, b, wb, bad);
+        if (wa == wb || bad) return;
+        const uint64_t hi = max(wa, wb), lo = min(wa, wb);
+        const uint64_t old = min_coherent64(nodes + node_of(hi), lo);
+        if (old == hi) return;
+        // hi was hooked meanwhile: join its new parent with lo instead
+        a = node_of(old);
+        b = node_of(lo);
+        if (a >= n) break;
+        wa = nodes[a];
+        wb = lo;
     }
-    bad |= p != x;
-    return x;
+    bad = true;
 }
 
 // ------------------------------------------------------------ spin staging
@@ -329,7 +422,7 @@ struct UnionQueue {
 };
 
 // Run the queued unions, one per lane.
-__device__ __forceinline__ void drain(UnionQueue& uq, uint32_t* P, uint32_t lane, bool& bad)
+__device__ __forceinline__ void drain(UnionQueue& uq, uint16_t* P, uint32_t lane, bool& bad)
 {
     for (uint32_t j = lane; j < uq.n; j += 64) {
         const uint32_t e = lds_ld(&uq.q[j]);
@@ -358,7 +451,7 @@ __device__ __forceinline__ void enqueue(UnionQueue& uq, uint64_t mask, uint32_t 
 // run from a differently labelled site queues a union.  Every site's own
 // union-find entry points at its label (itself for a new root), so the forest
 // spans all sites and no separate array of provisional labels is kept.
-__device__ __forceinline__ uint32_t row_labels(uint32_t* P, uint32_t* rl, UnionQueue& uq, uint32_t r, uint32_t x,
+__device__ __forceinline__ uint32_t row_labels(uint16_t* P, uint32_t* rl, UnionQueue& uq, uint32_t r, uint32_t x,
                                                uint64_t validm, uint64_t hx, uint64_t V, uint64_t hprev, uint32_t lp)
 {
     const uint64_t C = hx << 1;                 // bit x: bond (x-1) -> x
@@ -395,14 +488,14 @@ __device__ __forceinline__ uint32_t row_labels(uint32_t* P, uint32_t* rl, UnionQ
 // flags bit 0: also measure the configuration the bonds are drawn on (the
 // result of the previous sweep, t - 1).
 template <int TY>
-__global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* descs, const WorkItem* map, uint32_t k,
+__global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_eu(8))) void k_bond_label(const LatDesc* descs, const WorkItem* map, uint32_t k,
                                                    uint32_t flags)
 {
     constexpr uint32_t NW = waves_of<TY>(), NT = threads_of<TY>();
     constexpr uint32_t RPW = TY / NW;  // rows per wave (even)
     static_assert(RPW < 32, "per-lane measurement counters hold at most 31 rows");
     constexpr uint32_t QCAP = qcap_of<TY>();
-    __shared__ uint32_t P[TY * TX];    // union-find over the tile's sites
+    __shared__ __align__(16) uint16_t P[TY * TX];   // union-find over the tile's sites
     __shared__ __align__(16) uint8_t sp[(TY + 1) * SPW];
     __shared__ uint64_t rb[TY][2];     // per row: +x bond word, +y bond word
     // per wave: the label of every run of a row; once a wave has left its
@@ -412,7 +505,7 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
     uint32_t(*const seam)[65] = RL;
     __shared__ uint32_t UQ[NW][QCAP];  // per wave: pending unions
     __shared__ uint32_t hist[256];
-    __shared__ uint32_t tot[2];
+    __shared__ uint32_t tot[3];        // unequal pairs, active bonds, edge-forest nodes
 
     LatDesc d;
     uint32_t tile, lat;
@@ -425,7 +518,7 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
     const uint32_t L = d.L, w = g.w, h = g.h, x0 = g.x0, y0 = g.y0;
 
     if (tid < 256) hist[tid] = 0;
-    if (tid < 2) tot[tid] = 0;
+    if (tid < 3) tot[tid] = 0;
     stage_spins<TY>(sp, d, g, tid);
     __syncthreads();
 
@@ -600,50 +693,103 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
     }
     __syncthreads();
 
-    // Labels out: every site gets its union-find grandparent as a global site
-    // index (a smaller site of its tile-local cluster, or itself for the
-    // tile-local root); the flip follows these pointers inside the tile.  Entries of
-    // columns outside the tile are never stored (full-width tiles, the common
-    // case, need no mask at all).
+    // Edge sites find their tile-local roots (lane i takes the left and right
+    // sites of strip row i; the first and last strips the top and bottom rows).
+    // The first lane to reach a root claims it as a node of the tile's edge
+    // forest: it takes the next slot (in no particular order: a node's word
+    // carries its key), writes the node's word (a root of its own, keyed by its
+    // site index) and tags the root's LDS entry ROOT | slot, which the labels
+    // and the edge record copy.  Walks stop at tagged entries.
     // a site index fits 32 bits (N <= 2^32) and y, L fit 24 bits
     auto global_index = [&](uint32_t la) { return __umul24(y0 + la / TX, L) + x0 + la % TX; };
-    auto parents_out = [&](auto full) {
+    const uint32_t node0 = tile * nslot(TY);
+    auto edge_root = [&](uint32_t li) {
+        uint32_t p = lds_ld(&P[li]);
+        while (!(p & ROOT16) && p < li) {
+            li = p;
+            p = lds_ld(&P[li]);
+        }
+        bad |= !(p & ROOT16) && p != li;
+        return li;
+    };
+    // claim root r if it is still untagged: one swap per lane, then the wave's
+    // winners take consecutive slots with one LDS atomic
+    auto claim = [&](bool want, uint32_t r) {
+        const bool won = want && lds_cas16(P, r, r, ROOT16 | NOSLOT, bad) == r;
+        const uint64_t m = ballot(won);
+        if (!m) return;
+        uint32_t base = 0;
+        if (lane == 0) base = atomicAdd(&tot[2], popc64(m));
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (won) {
+            const uint32_t slot = base + lanes_below(m);
+            glb(d.nodes)[node0 + slot] = ((uint64_t)global_index(r) << 32) | (node0 + slot);
+            lds_st(&P[r], ROOT16 | slot);
+        }
+    };
+    const bool side = r0 < r1 && lane < r1 - r0;
+    const bool top = r0 == 0 && r0 < r1 && vx;
+    const bool bottom = r1 == h && r0 < r1 && vx;
+    const uint32_t rs = r0 + lane;
+    const uint32_t rootR = side ? edge_root(rs * TX + w - 1) : 0u;
+    const uint32_t rootL = side ? edge_root(rs * TX) : 0u;
+    const uint32_t rootT = top ? edge_root(x) : 0u;
+    const uint32_t rootB = bottom ? edge_root((h - 1) * TX + x) : 0u;
+    claim(side, rootR);
+    claim(side, rootL);
+    claim(top, rootT);
+    claim(bottom, rootB);
+    __syncthreads();
+    if (tid == 0) rec[6] = tot[2];   // nodes of the tile
+
+    // Labels out, per site: the tile-local index of its union-find grandparent
+    // (a smaller site of its tile-local cluster; the flip follows these
+    // pointers inside the tile), or, for a tile-local root, ROOT | its slot
+    // (NOSLOT if its cluster touches no tile edge).  A grandparent that is a
+    // node is not copied (its entry carries a slot, not an index): the parent
+    // is.  (The grandparent read is masked into the tile: a tagged entry's
+    // slot, or an unused column's entry, reads some entry that is not used.)
+    // Entries of columns outside the tile are never stored (full-width tiles,
+    // the common case, need no mask at all).
+    auto label_of = [&](uint32_t li, uint32_t p, uint32_t gp) {
+        return (p & ROOT16) ? (ROOT | (p & ~ROOT16)) : (p == li) ? (ROOT | NOSLOT) : (gp & ROOT16) ? p : gp;
+    };
+    auto labels_out = [&](auto full) {
         constexpr bool FULL = decltype(full)::value;
         const bool vs = FULL || vx;
         for (uint32_t r = r0; r < r1; ++r) {
-            // the grandparent: one more read here saves the flip a longer walk
-            const uint32_t ga = global_index(P[P[r * TX + x]]);
+            const uint32_t li = r * TX + x, p = P[li];
+            const uint32_t out = label_of(li, p, P[p & (TY * TX - 1u)]);
             const gptr<uint32_t> lrow = glb(d.lab) + (size_t)(y0 + r) * L + x0;
-            if (vs) lrow[x] = ga;
+            if (vs) lrow[x] = out;
         }
     };
     if (w == TX && r1 - r0 == RPW) {
         // a full strip: all parent reads first, then all grandparent reads, so
         // the LDS round trips overlap; the stores go out from the strip's
         // (wave-uniform) base with 32-bit per-lane offsets
-        uint32_t p[RPW];
+        uint32_t p[RPW], gp[RPW];
 #pragma unroll
-        for (uint32_t k = 0; k < RPW; ++k) p[k] = P[(r0 + k) * TX + x];
+        for (uint32_t k = 0; k < RPW; ++k) p[k] = P[(r0 + k) * TX + x];   // (16-bit entries)
 #pragma unroll
-        for (uint32_t k = 0; k < RPW; ++k) p[k] = P[p[k]];
+        for (uint32_t k = 0; k < RPW; ++k) gp[k] = P[p[k] & (TY * TX - 1u)];
         const gptr<char> strip = (gptr<char>)(glb(d.lab) + (size_t)(y0 + r0) * L + x0);
 #pragma unroll
-        for (uint32_t k = 0; k < RPW; ++k) *(gptr<uint32_t>)(strip + (k * L + x) * 4u) = global_index(p[k]);
+        for (uint32_t k = 0; k < RPW; ++k)
+            *(gptr<uint32_t>)(strip + (k * L + x) * 4u) = label_of((r0 + k) * TX + x, p[k], gp[k]);
     } else if (w == TX) {
-        parents_out(std::true_type{});
+        labels_out(std::true_type{});
     } else {
-        parents_out(std::false_type{});
+        labels_out(std::false_type{});
     }
-    // The tile's edges for the merge carry tile-local roots: lane i walks the
-    // left and right sites of strip row i; the first and last strips walk the
-    // top and bottom rows.
-    if (r0 < r1 && lane < r1 - r0) {
-        const uint32_t r = r0 + lane;
-        rec[8 + r] = global_index(lds_root(P, r * TX + w - 1, bad));
-        rec[8 + TY + r] = global_index(lds_root(P, r * TX, bad));
+    // The edge record's slots, for the merge.
+    const gptr<uint16_t> slots = (gptr<uint16_t>)(rec + 8);
+    if (side) {
+        slots[rs] = P[rootR] & ~ROOT16;
+        slots[TY + rs] = P[rootL] & ~ROOT16;
     }
-    if (r0 == 0 && r0 < r1 && vx) rec[8 + 2 * TY + TX + x] = global_index(lds_root(P, x, bad));   // top row
-    if (r1 == h && r0 < r1 && vx) rec[8 + 2 * TY + x] = global_index(lds_root(P, (h - 1) * TX + x, bad));   // bottom
+    if (top) slots[2 * TY + TX + x] = P[rootT] & ~ROOT16;
+    if (bottom) slots[2 * TY + x] = P[rootB] & ~ROOT16;
     if (bad) flag_error(d.err);
 
     if (meas) {
@@ -659,7 +805,8 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_bond_label(const LatDesc* 
 
 // ---------------------------------------------------------------------------
 // Join tile-local clusters across tile edges.  One wave per tile handles the
-// crossing bonds of its right and bottom edges (periodic neighbours).
+// crossing bonds of its right and bottom edges (periodic neighbours): each
+// joins the edge-forest nodes of the two sites' tile-local roots.
 template <int TY>
 __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkItem* map, uint32_t nitems)
 {
@@ -670,69 +817,82 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
     uint32_t tile, lat;
     if (!pick(descs, map, idx, false, d, tile, lat)) return;
     const TileGeom g = tile_geom(d, tile, TY);
-    const uint32_t EW = edge_words(TY);
-    const uint64_t N = (uint64_t)d.L * d.L;
+    const uint32_t EW = edge_words(TY), NS = nslot(TY);
+    const uint32_t n = d.ntiles * NS;
     const uint32_t t_right = g.ty * d.ntx + ((g.tx + 1 == d.ntx) ? 0u : g.tx + 1);
     const uint32_t t_below = ((g.ty + 1 == d.nty) ? 0u : g.ty + 1) * d.ntx + g.tx;
     const gptr<uint32_t> rec = glb(d.edges) + (size_t)tile * EW;
-    const gptr<uint32_t> recR = glb(d.edges) + (size_t)t_right * EW;
-    const gptr<uint32_t> recB = glb(d.edges) + (size_t)t_below * EW;
+    const gptr<const uint16_t> sl = (gptr<const uint16_t>)(rec + 8);
+    const gptr<const uint16_t> slR = (gptr<const uint16_t>)(glb(d.edges) + (size_t)t_right * EW + 8);
+    const gptr<const uint16_t> slB = (gptr<const uint16_t>)(glb(d.edges) + (size_t)t_below * EW + 8);
+    const gptr<uint64_t> nodes = glb(d.nodes);
 
+    // Lane l takes the crossing bond of row l of the right edge (row l of the
+    // right neighbour's left column) and of column l of the bottom edge
+    // (column l of the top row of the tile below); consecutive crossing bonds
+    // between the same two clusters are joined once.  The nodes' words are all
+    // loaded before the first union, so their round trips overlap.
     bool bad = false;
-    // Right edge: row r joins (w-1, r) here with (0, r) of the right neighbour.
     uint32_t pa = INVALID, pb = INVALID;
     for (uint32_t j = 0; j < TY; j += 64) {
-        const uint32_t r = j + lane;
-        const bool bit = r < g.h && ((rec[r >> 5] >> (r & 31u)) & 1u);
-        uint32_t a = INVALID, b = INVALID;
-        if (bit) {
-            a = rec[8 + r];
-            b = recR[8 + TY + r];
+        const uint32_t r = j + lane, x = lane;
+        const bool right = r < g.h && ((rec[r >> 5] >> (r & 31u)) & 1u);
+        const bool below = j == 0 && x < g.w && ((rec[4 + (x >> 5)] >> (x & 31u)) & 1u);
+        uint32_t a1 = INVALID, b1 = INVALID, a2 = INVALID, b2 = INVALID;
+        if (right) {
+            a1 = tile * NS + sl[r];
+            b1 = t_right * NS + slR[TY + r];
         }
-        uint32_t ua = __shfl_up(a, 1), ub = __shfl_up(b, 1);
+        if (below) {
+            a2 = tile * NS + sl[2 * TY + x];
+            b2 = t_below * NS + slB[2 * TY + TX + x];
+        }
+        uint32_t ua = __shfl_up(a1, 1), ub = __shfl_up(b1, 1);
+        uint32_t va = __shfl_up(a2, 1), vb = __shfl_up(b2, 1);
         if (lane == 0) {
             ua = pa;
             ub = pb;
+            va = INVALID;
+            vb = INVALID;
         }
-        pa = __shfl(a, 63);
-        pb = __shfl(b, 63);
-        // consecutive crossing bonds between the same two clusters: join once
-        if (bit && !(ua == a && ub == b)) g_unite(glb(d.lab), N, a, b, bad);
-    }
-    // Bottom edge: column x joins (x, h-1) here with (x, 0) of the tile below.
-    {
-        const uint32_t x = lane;
-        const bool bit = x < g.w && ((rec[4 + (x >> 5)] >> (x & 31u)) & 1u);
-        uint32_t a = INVALID, b = INVALID;
-        if (bit) {
-            a = rec[8 + 2 * TY + x];
-            b = recB[8 + 2 * TY + TX + x];
-        }
-        uint32_t ua = __shfl_up(a, 1), ub = __shfl_up(b, 1);
-        if (lane == 0) {
-            ua = INVALID;
-            ub = INVALID;
-        }
-        if (bit && !(ua == a && ub == b)) g_unite(glb(d.lab), N, a, b, bad);
+        pa = __shfl(a1, 63);
+        pb = __shfl(b1, 63);
+        const bool u1 = right && !(ua == a1 && ub == b1) && a1 < n && b1 < n;
+        const bool u2 = below && !(va == a2 && vb == b2) && a2 < n && b2 < n;
+        bad |= (right && !(a1 < n && b1 < n)) || (below && !(a2 < n && b2 < n));
+        const uint64_t wa1 = u1 ? nodes[a1] : 0ull, wb1 = u1 ? nodes[b1] : 0ull;
+        const uint64_t wa2 = u2 ? nodes[a2] : 0ull, wb2 = u2 ? nodes[b2] : 0ull;
+        if (u1) n_unite(nodes, n, a1, b1, wa1, wb1, bad);
+        if (u2) n_unite(nodes, n, a2, b2, wa2, wb2, bad);
     }
     if (bad) flag_error(d.err);
 }
 
 // ---------------------------------------------------------------------------
 // Flip: every site takes the state drawn for the smallest site index of its
-// cluster.  Inside the tile the labels form a forest whose terminals are the
-// sites that are global roots or whose parent lies outside the tile; only the
-// terminals search the global forest (halving the paths they walk) and draw a
-// state, in compacted lanes.  Wave w owns rows w, w+4, w+8, ... (lane =
-// column); its labels are all loaded first, and its terminals go to a list of
-// its own.
+// cluster.  Inside the tile the labels form a forest of tile-local indices
+// whose terminals are the tile-local roots.  The tile's edge-forest nodes are
+// loaded together at the start (node j by lane j / NW of wave j % NW) and
+// search their roots (halving the paths they walk); then each wave draws, in
+// compacted lanes, the states of its nodes (keyed by their roots) and of the
+// roots of clusters inside the tile it found (keyed by their own sites).
+// Wave w owns rows w, w+4, w+8, ... (lane = column); its labels are all
+// loaded first.  LDS entries are 16 bits (so more workgroups fit a CU): a
+// tile-local index, ROOT16 | slot for a node, ROOT16 | RES16 | state for a
+// resolved root inside the tile.
 template <int TY>
-__global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs, const WorkItem* map, uint32_t k)
+__global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_eu(8))) void k_flip(
+    const LatDesc* descs, const WorkItem* map, uint32_t k)
 {
     constexpr uint32_t NW = waves_of<TY>(), NT = threads_of<TY>();
-    constexpr uint32_t PER = TY / NW;  // rows per wave
-    __shared__ uint32_t E[TY * TX];
-    __shared__ uint16_t list[NW][PER * TX + 64];   // + a scratch slot per lane
+    constexpr uint32_t PER = TY / NW;       // rows per wave
+    constexpr uint32_t RES16 = 0x4000u;     // a resolved root inside the tile
+    constexpr uint32_t NKN = 512;           // node table (>= nslot(TY), a power of two)
+    constexpr uint32_t NODE_ENTRY = 0x8000u;   // a list entry that names a node
+    static_assert(nslot(TY) <= NKN && nslot(TY) <= NT && nslot(TY) < RES16, "one thread per node");
+    __shared__ uint16_t E[TY * TX];
+    __shared__ uint16_t list[NW][PER * TX + 64 + 64];   // roots inside the tile, nodes, a scratch slot per lane
+    __shared__ uint32_t NK[NKN];            // per node: its root's key, then its state
 
     LatDesc d;
     uint32_t tile, lat;
@@ -743,11 +903,10 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
     const uint32_t L = d.L, w = g.w, h = g.h, x0 = g.x0, y0 = g.y0;
     const uint32_t col = lane;
     uint16_t* my_list = list[wave];
-    const gptr<uint32_t> lab = glb(d.lab);
+    const uint32_t NS = nslot(TY), n_nodes = d.ntiles * NS, node0 = tile * NS;
+    const gptr<uint64_t> nodes = glb(d.nodes);
     bool bad = false;
 
-    // Full tiles (the common case) need no masks for columns or rows outside;
-    // a power-of-two L divides by a shift.
     // The tile's entries are addressed from a wave-uniform base with 32-bit
     // per-lane byte offsets (a tile spans fewer than 2^32 / 4 sites of the
     // arrays), which keeps 64-bit address arithmetic out of the vector units.
@@ -755,10 +914,11 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
     const uint32_t wave_step = NW * L;             // sites between a wave's consecutive rows
     const gptr<const char> lab_tile = (gptr<const char>)(glb(d.lab) + (size_t)y0 * L + x0);
     const gptr<char> s_tile = (gptr<char>)(glb(d.s) + (size_t)y0 * L + x0);
+    const uint32_t n_used = min(glb(d.edges)[(size_t)tile * edge_words(TY) + 6], NS);
 
-    auto body = [&](auto full, auto pow2) {
+    // Full tiles (the common case) need no masks for columns or rows outside.
+    auto body = [&](auto full) {
         constexpr bool FULL = decltype(full)::value;
-        constexpr bool POW2 = decltype(pow2)::value;
         const bool vcol = FULL || col < w;
         uint32_t v[PER];
 #pragma unroll
@@ -767,74 +927,70 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
             const uint32_t byte_off = (site0 + j * wave_step) * 4u;
             v[j] = (vcol && (FULL || r < h)) ? *(gptr<const uint32_t>)(lab_tile + byte_off) : 0u;
         }
+        const uint32_t nj = lane * NW + wave;   // this lane's node
+        const bool is_node = nj < n_used;
+        const uint64_t nw = is_node ? nodes[node0 + nj] : 0ull;
 
-        // row j of this wave: tile index li0 + j NW TX, site index gi0 + j wave_step
-        // (site indices fit 32 bits, N <= 2^32; rows and L fit 24 bits)
+        // row j of this wave: tile index li0 + j NW TX
         const uint32_t li0 = wave * TX + col;
-        const uint32_t gi0 = __umul24(y0 + wave, L) + x0 + col;
         uint32_t nterm = 0;   // wave-uniform
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
             const uint32_t r = wave + NW * j;
             if (!FULL && r >= h) continue;
             const uint32_t li = li0 + j * NW * TX;
-            const uint32_t gi = gi0 + j * wave_step;
             const uint32_t vv = v[j];
-            bool term;
-            uint32_t local;
-            if (FULL && POW2) {
-                // power-of-two L, aligned full tile: the label is inside iff it
-                // agrees with the site's own index outside the in-tile bits
-                const uint32_t inner = ((uint32_t)(TY - 1) << d.log2L) | (TX - 1u);
-                term = vv == gi || ((vv ^ gi) & ~inner) != 0u;
-                local = (((vv >> d.log2L) & (TY - 1u)) * TX) | (vv & (TX - 1u));
-            } else {
-                // tile coordinates of the label (meaningless, and rejected, outside the tile)
-                const uint32_t vy = POW2 ? vv >> d.log2L : div_L(d, vv);
-                const uint32_t dy = vy - y0, dx = (POW2 ? (vv & (L - 1u)) : vv - __umul24(vy, L)) - x0;
-                term = vcol && (vv == gi || dy >= (FULL ? TY : h) || dx >= (FULL ? TX : w));
-                local = dy * TX + dx;
-            }
-            const uint64_t m = ballot(term);
-            const bool is_term = lane_in(m);
-            if (vcol) E[li] = is_term ? vv : local;
-            // terminals append to the list, the other lanes write their scratch slot
-            const uint32_t at_list = nterm + lanes_below(m), at_scratch = PER * TX + lane;
-            my_list[is_term ? at_list : at_scratch] = (uint16_t)li;
+            const bool root = (vv & ROOT) != 0u;
+            const uint32_t slot = vv & 0xFFFFu;
+            // a pointer must go to a smaller site, a slot to a node of the tile
+            bad |= vcol && (root ? (slot != NOSLOT && slot >= n_used) : vv >= li);
+            const uint64_t m = ballot(vcol && root && slot == NOSLOT);
+            if (vcol) E[li] = root ? (ROOT16 | (slot & 0x7FFFu)) : vv;
+            // roots inside the tile append to the list, the other lanes write their scratch slot
+            const uint32_t at_list = nterm + lanes_below(m), at_scratch = PER * TX + 64 + lane;
+            my_list[lane_in(m) ? at_list : at_scratch] = (uint16_t)li;
+            nterm = __builtin_amdgcn_readfirstlane(nterm + popc64(m));
+        }
+        // this wave's nodes find their roots' keys and join the list
+        if (is_node) NK[nj] = key_of(n_find_from(nodes, n_nodes, node0 + nj, nw, bad));
+        {
+            const uint64_t m = ballot(is_node);
+            const uint32_t at_list = nterm + lanes_below(m), at_scratch = PER * TX + 64 + lane;
+            my_list[lane_in(m) ? at_list : at_scratch] = (uint16_t)(NODE_ENTRY | nj);
             nterm = __builtin_amdgcn_readfirstlane(nterm + popc64(m));
         }
 
-        // a wave resolves the terminals it found (all its own entries of E),
-        // 64 at a time; lanes past the end work on a copy they do not store
+        // the states, 64 list entries at a time; lanes past the end work on a
+        // copy they do not store
         for (uint32_t j0 = 0; j0 < nterm; j0 += 64) {
             const uint32_t j = j0 + lane;
             const bool act = j < nterm;
-            const uint32_t li = my_list[act ? j : 0];
-            const uint32_t vv = E[li];
-            const uint32_t gi = __umul24(y0 + li / TX, L) + x0 + li % TX;
-            uint32_t root = vv;
-            if (act && vv < gi) root = g_find(lab, vv, bad);
-            bad |= act && vv > gi;
-            const uint32_t st = TERM | cluster_state(d, root, t);
-            if (act) E[li] = st;
+            const uint32_t e = my_list[act ? j : 0];
+            const bool node = (e & NODE_ENTRY) != 0u;
+            const uint32_t idx = e & ~NODE_ENTRY;
+            const uint32_t key = node ? NK[idx & (NKN - 1u)] : __umul24(y0 + idx / TX, L) + x0 + idx % TX;
+            const uint32_t st = cluster_state(d, key, t);
+            if (act && node) NK[idx & (NKN - 1u)] = st;
+            if (act && !node) E[idx & (TY * TX - 1u)] = ROOT16 | RES16 | st;
         }
         __syncthreads();
 
         // Every site follows in-tile pointers (each to a smaller tile index, so
-        // the walk ends) to a resolved entry; the new spins are stored at the end.
+        // the walk ends) to a root: resolved inside the tile, or a node whose
+        // state is in the table; the new spins are stored at the end.
         uint32_t e[PER];
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
             const uint32_t r = wave + NW * j;
-            e[j] = TERM;
+            e[j] = 0;
             if (vcol && (FULL || r < h)) {
                 uint32_t cur = li0 + j * NW * TX, x = E[cur];
-                while (!(x & TERM) && x < cur) {
+                while (!(x & ROOT16) && x < cur) {
                     cur = x;
                     x = E[cur];
                 }
-                bad |= !(x & TERM);
-                e[j] = x;
+                bad |= !(x & ROOT16);
+                e[j] = (x & RES16) ? x : NK[x & (NKN - 1u)];
             }
         }
 #pragma unroll
@@ -843,12 +999,8 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_flip(const LatDesc* descs,
             if (vcol && (FULL || r < h)) *(gptr<uint8_t>)(s_tile + (site0 + j * wave_step)) = (uint8_t)e[j];
         }
     };
-    if (w == TX && h == TY) {
-        if (d.log2L) body(std::true_type{}, std::true_type{});
-        else body(std::true_type{}, std::false_type{});
-    } else {
-        body(std::false_type{}, std::false_type{});
-    }
+    if (w == TX && h == TY) body(std::true_type{});
+    else body(std::false_type{});
     if (bad) flag_error(d.err);
 
     // The ring record of the next sweep starts from zero.
@@ -926,17 +1078,46 @@ __global__ __launch_bounds__(256) void k_init(const LatDesc* descs, uint32_t lat
     }
 }
 
-// Labels of the last sweep resolved to the smallest site index of each cluster.
-__global__ __launch_bounds__(256) void k_resolve(const LatDesc* descs, uint32_t lat)
+// Labels of the last sweep resolved, in place, to the smallest site index of
+// each cluster: one workgroup per tile walks its sites' pointers in LDS to
+// their tile-local roots and those, if they are nodes, to the edge forest's
+// roots.  The sweep does not read the labels again before it writes them anew.
+template <int TY>
+__global__ __launch_bounds__(threads_of<TY>()) void k_resolve(const LatDesc* descs, uint32_t lat)
 {
+    constexpr uint32_t NT = threads_of<TY>();
+    __shared__ uint32_t E[TY * TX];
     const LatDesc d = descs[lat];
-    const size_t N = (size_t)d.L * d.L;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
-        const uint32_t v = glb(d.lab)[i];
-        bool bad = v > i;
-        if (!bad) glb(d.lab)[i] = g_root(glb(d.lab), v, bad);
-        if (bad) flag_error(d.err);
+    const uint32_t tile = blockIdx.x;
+    if (tile >= d.ntiles) return;
+    const TileGeom g = tile_geom(d, tile, TY);
+    const uint32_t NS = nslot(TY), n_nodes = d.ntiles * NS, node0 = tile * NS;
+    const gptr<uint32_t> lab = glb(d.lab);
+    bool bad = false;
+    for (uint32_t li = threadIdx.x; li < TY * TX; li += NT) {
+        const uint32_t r = li / TX, c = li % TX;
+        E[li] = (r < g.h && c < g.w) ? lab[(size_t)(g.y0 + r) * d.L + g.x0 + c] : (ROOT | NOSLOT);
     }
+    __syncthreads();
+    for (uint32_t li = threadIdx.x; li < TY * TX; li += NT) {
+        const uint32_t r = li / TX, c = li % TX;
+        if (r >= g.h || c >= g.w) continue;
+        uint32_t cur = li, v = E[cur];
+        while (!(v & ROOT) && v < cur) {
+            cur = v;
+            v = E[cur];
+        }
+        uint32_t root = INVALID;
+        if (!(v & ROOT)) {
+            bad = true;
+        } else if ((v & 0xFFFFu) == NOSLOT) {
+            root = (g.y0 + cur / TX) * d.L + g.x0 + cur % TX;
+        } else {
+            root = key_of(n_root(glb(d.nodes), n_nodes, node0 + (v & 0xFFFFu), bad));
+        }
+        lab[(size_t)(g.y0 + r) * d.L + g.x0 + c] = root;
+    }
+    if (bad) flag_error(d.err);
 }
 
 // One thread per (record, word): the sum of the word over the record's NCOPY
@@ -1076,9 +1257,14 @@ hipError_t launch_init(const LatDesc* descs, uint32_t lat, size_t N, uint32_t ra
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, size_t N, hipStream_t s)
+hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, uint32_t ntiles, uint32_t ty, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_resolve, dim3(init_grid(N)), dim3(256), 0, s, descs, lat);
+    switch (ty) {
+    case 32: hipLaunchKernelGGL(k_resolve<32>, dim3(ntiles), dim3(threads_of<32>()), 0, s, descs, lat); break;
+    case 64: hipLaunchKernelGGL(k_resolve<64>, dim3(ntiles), dim3(threads_of<64>()), 0, s, descs, lat); break;
+    case 128: hipLaunchKernelGGL(k_resolve<128>, dim3(ntiles), dim3(threads_of<128>()), 0, s, descs, lat); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -26,7 +26,8 @@ hipError_t launch_measure(const Work& w, uint32_t k);
 // measurement after n_each[lattice] sweeps of each lattice (batched form)
 hipError_t launch_measure_each(const Work& w, const uint32_t* n_each);
 hipError_t launch_init(const LatDesc* descs, uint32_t lat, size_t N, uint32_t random_start, hipStream_t s);
-hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, size_t N, hipStream_t s);
+// Labels of the last sweep resolved in place to smallest site indices.
+hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, uint32_t ntiles, uint32_t ty, hipStream_t s);
 // Sum the NCOPY partial copies of n ring records, from slot slot0 on (wrapping
 // at `slots`), into out[n][q + 1].
 hipError_t launch_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, uint32_t slot0, uint32_t n, uint32_t q,

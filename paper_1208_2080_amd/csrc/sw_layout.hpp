@@ -1,14 +1,25 @@
 // Data layout of one lattice in device memory, shared by kernels and host runtime.
 //
-// Per lattice (site i = y*L + x, row-major):
+// Per lattice (site i = y*L + x, row-major; tiles of TX = 64 columns by TY
+// rows, numbered row-major; a site's tile-local index is r*TX + c for row r,
+// column c of its tile):
 //   spins   uint8  [N]
-//   labels  uint32 [N]        after a sweep: every site holds a smaller site of
-//                             its tile-local cluster (its union-find parent
-//                             within the tile); tile-local roots hold their
-//                             parent in the global forest (themselves if none)
+//   labels  uint32 [N]        after a sweep, per site: the tile-local index of a
+//                             smaller site of its tile-local cluster (its
+//                             union-find grandparent in the tile), or, for the
+//                             cluster's smallest site (its tile-local root),
+//                             ROOT | slot, slot the root's node in the tile's
+//                             edge forest, NOSLOT if the cluster touches no
+//                             tile edge
 //   bonds   uint64 [tiles][2][TY]  tile-major bond words: tile t, plane p (0: +x,
 //                             1: +y), row r; bit x = bond of site (x0 + x, y0 + r)
-//   edges   uint32 [tiles][EDGE_WORDS(TY)]  per-tile boundary record (below)
+//   edges   uint32 [tiles][edge_words(TY)]  per-tile boundary record (below)
+//   nodes   uint64 [tiles][nslot(TY)]  the edge forest: one node per tile-local
+//                             cluster that touches a tile edge, numbered by its
+//                             smallest site within the tile; a node's word is
+//                             (smallest site index of its parent << 32) | parent
+//                             node id, a root's parent being itself, so the
+//                             forest's roots are the clusters' smallest sites
 //   ring    int64  [slots][NCOPY][ring_stride(q)]  per-sweep sums: n_unsat,
 //                             n_active, n_1..n_{q-1} (n_0 = N - the rest);
 //                             NCOPY partial copies, each on cache lines of its
@@ -16,7 +27,7 @@
 //   obs     int64  [slots][q + 1]  staging for reads: the NCOPY partial copies of
 //                             the records being read, summed on the device
 //   state   DevState          sweep counter and error flag
-// Tiles are TX = 64 columns by TY rows (TY = 32, 64 or 128), numbered row-major.
+// TY = 32, 64 or 128.
 #pragma once
 
 #include <stdint.h>
@@ -25,18 +36,25 @@ namespace swmi {
 
 constexpr uint32_t TX = 64;           // tile width: one wave, one column per lane
 constexpr uint32_t NCOPY = 64;        // partial copies of each ring record
-constexpr uint32_t TERM = 0x80000000u;
+constexpr uint32_t TERM = 0x80000000u;     // flip: entry resolved to a state
+constexpr uint32_t ROOT = 0x80000000u;     // label of a tile-local root
+constexpr uint32_t NOSLOT = 0x7FFFu;       // root of a cluster inside its tile
+constexpr uint32_t ROOT16 = 0x8000u;       // tile-local root's tag in 16-bit entries
 constexpr uint32_t INVALID = 0xFFFFFFFFu;
 
-// Boundary record of a tile with TY rows (uint32 words):
-//   [0, 4)            right-edge crossing bonds, bit r = +x bond of (w-1, r)
-//   [4, 6)            bottom-edge crossing bonds, bit x = +y bond of (x, h-1)
-//   [6, 8)            unused
-//   [8, 8+TY)         labels of the right column
-//   [8+TY, 8+2TY)     labels of the left column
-//   [8+2TY, +TX)      labels of the bottom row
-//   [8+2TY+TX, +TX)   labels of the top row
-__host__ __device__ constexpr uint32_t edge_words(uint32_t ty) { return 8u + 2u * ty + 2u * TX; }
+// Boundary record of a tile with TY rows: 8 uint32 words, then uint16 slots
+// (edge-forest nodes of the tile-local roots) of its edge sites:
+//   words [0, 4)      right-edge crossing bonds, bit r = +x bond of (w-1, r)
+//   words [4, 6)      bottom-edge crossing bonds, bit x = +y bond of (x, h-1)
+//   words [6, 8)      unused
+//   slots [0, TY)           right column, by row
+//   slots [TY, 2TY)         left column, by row
+//   slots [2TY, 2TY+TX)     bottom row, by column
+//   slots [2TY+TX, 2TY+2TX) top row, by column
+__host__ __device__ constexpr uint32_t edge_words(uint32_t ty) { return 8u + ty + TX; }
+
+// Nodes of a tile's edge forest: at most one per edge site.
+__host__ __device__ constexpr uint32_t nslot(uint32_t ty) { return 2u * TX + 2u * ty; }
 
 // int64 words between partial copies of a ring record: the q + 1 sums rounded
 // up to whole 256-byte blocks, so no two copies share a cache line.
@@ -53,6 +71,7 @@ struct LatDesc {
     uint32_t* lab;
     uint64_t* bonds;
     uint32_t* edges;
+    uint64_t* nodes;       // edge forest, nslot(TY) words per tile
     int64_t* ring;
     int64_t* obs;          // staging of summed ring records (reads only)
     uint32_t* counter;     // sweeps done

@@ -164,22 +164,37 @@ def test_errors_surface_as_codes():
 
 
 def test_corrupted_label_forest_is_reported_not_walked():
-    # A label that points at a larger site breaks the forest invariant; the
-    # resolving walk must stop and report SW_ECONVERGE (every walk steps only to
-    # smaller indices, so it ends).  The corruption is written from the host
-    # into the workspace, between two calls.
+    # A label that points at a larger site of its tile breaks the forest
+    # invariant; the resolving walk must stop and report SW_ECONVERGE (every
+    # walk steps only to smaller indices, so it ends).  The corruption is
+    # written from the host into the workspace, between a sweep and the read.
     L = 16
     lat = binding.Lattice(L, 2, wl.critical_coupling(2), seed=3, obs_capacity=4)
     lat.sweep(1)
-    good = lat.labels()                      # resolves the forest in place
     # the labels follow the state (256 B), the descriptor (one 256-byte block)
     # and the spins (L*L bytes, 256-aligned) in the workspace
     off = 256 + 256 + ((L * L + 255) // 256) * 256
     words = lat.ws[off:off + 4 * L * L].view(torch.int32)
-    assert np.array_equal(words.cpu().numpy().view(np.uint32).reshape(L, L), good)
-    words[5] = L * L - 1                     # site 5 now points above itself
+    raw = words.cpu().numpy().view(np.uint32).reshape(L, L)
+    local = (np.arange(L)[:, None] * 64 + np.arange(L)[None, :]).astype(np.uint32)
+    # as stored by the sweep: a tile-local root's tag, or a smaller site of the tile
+    assert np.all((raw & np.uint32(0x80000000)) | (raw < local))
+    words[5] = 3 * 64 + 2                    # site 5 now points at a larger site of its tile
     torch.cuda.synchronize()
     with pytest.raises(binding.SwError) as e:
         lat.labels()
     assert e.value.code == binding.SW_ECONVERGE
+    lat.close()
+
+
+def test_labels_read_twice_and_after_more_sweeps():
+    L, q, K = 130, 3, wl.critical_coupling(3)
+    ref = oracle.OracleLattice(L, q, K, 21)
+    lat = binding.Lattice(L, q, K, seed=21, obs_capacity=4)
+    for _ in range(3):
+        lat.sweep(1)
+        out = ref.sweep()
+        assert np.array_equal(lat.labels(), out["labels"])
+        assert np.array_equal(lat.labels(), out["labels"])   # already resolved: the same again
+        assert np.array_equal(lat.spins(), ref.s)
     lat.close()
