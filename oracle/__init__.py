@@ -67,6 +67,11 @@ def lib():
         L.or_sweep.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64,
                                ctypes.c_uint32, u8p, u8p, u8p, u32p, i64p]
         L.or_sweep.restype = ctypes.c_int
+        L.or_bonds.argtypes = [ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32, u8p, u8p, u8p]
+        L.or_bonds.restype = ctypes.c_int
+        L.or_flip.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, u8p, u8p, u8p,
+                              u32p, i64p]
+        L.or_flip.restype = ctypes.c_int
         L.or_run.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64,
                              ctypes.c_uint32, ctypes.c_uint32, u8p, i64p]
         L.or_run.restype = ctypes.c_int
@@ -186,6 +191,27 @@ class OracleLattice:
         L = self.L
         return {"bx": self.bx.reshape(L, L).copy(), "by": self.by.reshape(L, L).copy(),
                 "labels": self.lab.reshape(L, L).copy(), "obs": obs}
+
+    def sweep_steps(self, progress=None) -> np.ndarray:
+        """One sweep as its three steps of Sec. 2, each a call of its own
+        (progress(name) after each, for long runs); returns the observables."""
+        obs = np.zeros(2 + self.q, dtype=np.int64)
+        flat = self.s.reshape(-1)
+        if lib().or_bonds(self.L, self.K, self.seed, self.t, _p(flat, ctypes.c_uint8), _p(self.bx, ctypes.c_uint8),
+                          _p(self.by, ctypes.c_uint8)) != 0:
+            raise ValueError("oracle bonds rejected its parameters")
+        if progress:
+            progress("bonds")
+        lib().or_label(self.L, _p(self.bx, ctypes.c_uint8), _p(self.by, ctypes.c_uint8), _p(self.lab, ctypes.c_uint32))
+        if progress:
+            progress("labels")
+        if lib().or_flip(self.L, self.q, self.seed, self.t, _p(flat, ctypes.c_uint8), _p(self.bx, ctypes.c_uint8),
+                         _p(self.by, ctypes.c_uint8), _p(self.lab, ctypes.c_uint32), _p(obs, ctypes.c_int64)) != 0:
+            raise ValueError("oracle flip rejected its parameters")
+        if progress:
+            progress("flip")
+        self.t += 1
+        return obs
 
     def run(self, n: int) -> np.ndarray:
         """n sweeps; returns the int64 observable rows [n, 2+q]."""

@@ -237,15 +237,12 @@ void or_label(uint32_t L, const uint8_t* bx, const uint8_t* by, uint32_t* label)
 
 /* ------------------------------------------------------------- one sweep */
 
-int or_sweep(uint32_t L, uint32_t q, double K, uint64_t seed, uint32_t sweep,
-             uint8_t* s, uint8_t* bx, uint8_t* by, uint32_t* label, int64_t* obs)
+/* Step (1) of Sec. 2: bond activation on equal-spin bonds with probability p. */
+int or_bonds(uint32_t L, double K, uint64_t seed, uint32_t sweep, const uint8_t* s, uint8_t* bx, uint8_t* by)
 {
-    if (L < 2 || q < 2 || q > 255 || !s || !bx || !by || !label) return -1;
+    if (L < 2 || !s || !bx || !by) return -1;
     uint64_t thr = or_threshold(K);
     if (thr == OR_BAD_THRESHOLD) return -1;
-    uint64_t N = (uint64_t)L * L;
-
-    /* step (1): bond activation on equal-spin bonds with probability p */
     for (uint32_t y = 0; y < L; ++y) {
         uint32_t yd = (y + 1 == L) ? 0 : y + 1;
         for (uint32_t x = 0; x < L; ++x) {
@@ -257,14 +254,18 @@ int or_sweep(uint32_t L, uint32_t q, double K, uint64_t seed, uint32_t sweep,
             by[i] = (s[i] == s[(uint64_t)yd * L + x]) && ((uint64_t)wy < thr);
         }
     }
+    return 0;
+}
 
-    /* step (2): cluster labels (root = smallest site index of the cluster) */
-    or_label(L, bx, by, label);
-
-    /* step (3): every cluster takes the new state drawn for its root */
+/* Step (3) of Sec. 2: every cluster takes the new state drawn for its root;
+ * then the observables of the new configuration (obs may be NULL). */
+int or_flip(uint32_t L, uint32_t q, uint64_t seed, uint32_t sweep, uint8_t* s, const uint8_t* bx,
+            const uint8_t* by, const uint32_t* label, int64_t* obs)
+{
+    if (L < 2 || q < 2 || q > 255 || !s || !bx || !by || !label) return -1;
+    uint64_t N = (uint64_t)L * L;
     for (uint64_t i = 0; i < N; ++i)
         s[i] = (uint8_t)or_newspin(seed, sweep, label[i], q);
-
     if (obs) {
         or_observe(L, q, s, obs);
         int64_t active = 0;
@@ -272,6 +273,15 @@ int or_sweep(uint32_t L, uint32_t q, double K, uint64_t seed, uint32_t sweep,
         obs[1] = active;
     }
     return 0;
+}
+
+int or_sweep(uint32_t L, uint32_t q, double K, uint64_t seed, uint32_t sweep,
+             uint8_t* s, uint8_t* bx, uint8_t* by, uint32_t* label, int64_t* obs)
+{
+    if (L < 2 || q < 2 || q > 255 || !s || !bx || !by || !label) return -1;
+    if (or_bonds(L, K, seed, sweep, s, bx, by) != 0) return -1;   /* step (1) */
+    or_label(L, bx, by, label);                                   /* step (2): root = smallest site index */
+    return or_flip(L, q, seed, sweep, s, bx, by, label, obs);     /* step (3) */
 }
 
 int or_run(uint32_t L, uint32_t q, double K, uint64_t seed, uint32_t first_sweep,

@@ -29,6 +29,9 @@ int or_init(uint32_t L, uint32_t q, uint64_t seed, int random_start, uint8_t* s)
 void or_observe(uint32_t L, uint32_t q, const uint8_t* s, int64_t* obs);
 void or_derived(uint32_t L, uint32_t q, const uint8_t* s, double* out);
 void or_label(uint32_t L, const uint8_t* bx, const uint8_t* by, uint32_t* label);
+int or_bonds(uint32_t L, double K, uint64_t seed, uint32_t sweep, const uint8_t* s, uint8_t* bx, uint8_t* by);
+int or_flip(uint32_t L, uint32_t q, uint64_t seed, uint32_t sweep, uint8_t* s, const uint8_t* bx,
+            const uint8_t* by, const uint32_t* label, int64_t* obs);
 int or_sweep(uint32_t L, uint32_t q, double K, uint64_t seed, uint32_t sweep,
              uint8_t* s, uint8_t* bx, uint8_t* by, uint32_t* label, int64_t* obs);
 int or_run(uint32_t L, uint32_t q, double K, uint64_t seed, uint32_t first_sweep,

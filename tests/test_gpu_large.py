@@ -11,8 +11,13 @@ benchmark times (default tile height).
   at most its site's index, the observables equal those of the spins; the
   clusters of sampled sites are rebuilt by breadth-first search over the bond
   planes and must carry exactly one label, their smallest site index.
+* L = 65536, q = 2 and q = 3, cold start, bit for bit: the oracle sweeps both
+  lattices twice (in two host threads, while the GPU sweeps), and the spins
+  (by a 64-bit hash of all 2^32 bytes) and the int64 observables must agree
+  after each sweep.
 """
 import collections
+import threading
 
 import numpy as np
 import pytest
@@ -203,3 +208,81 @@ def test_L65536_one_cluster_counts_need_64_bits(q):
     expect[2 + s_star] = L * L
     assert np.array_equal(obs, expect), obs
     lat.close()
+
+
+def _spin_hash(s) -> int:
+    import xxhash
+    return xxhash.xxh3_64_intdigest(memoryview(np.ascontiguousarray(s).reshape(-1)))
+
+
+@pytest.mark.timeout(1800)
+def test_L65536_bit_exact_two_sweeps(request):
+    """The largest configuration (2^32 sites, cold start, q = 2 and q = 3 at
+    their K_c) against the oracle after each of two sweeps: spins by a 64-bit
+    hash, observables exactly.  Host RAM: the oracle holds 7 bytes per site
+    per lattice (spins, two bond planes, labels: 28 GiB each, 56 GiB for both
+    at once) plus one 4 GiB copy of the GPU's spins at a time; the two oracle
+    lattices run in their own threads (a few minutes of one core per step), and
+    each finished step is reported as it happens (outside pytest's capture, so
+    that a long run shows its progress)."""
+    import queue
+
+    capture = request.config.pluginmanager.getplugin("capturemanager")
+
+    def live(msg):
+        if capture is None:
+            say(msg)
+            return
+        with capture.global_and_fixture_disabled():
+            print(msg, flush=True)
+
+    cfgs = [wl.HUGE_Q2, wl.HUGE_Q3]
+    ref_out = {}
+    events = queue.Queue()
+
+    def run_oracle(cfg):
+        q = cfg["q"]
+        try:
+            ref = oracle.OracleLattice(cfg["L"], q, cfg["K"], cfg["seed"], random_start=cfg["random_start"])
+            out = []
+            for t in range(2):
+                row = ref.sweep_steps(lambda step: events.put(f"  oracle q={q} sweep {t}: {step} done"))
+                out.append((_spin_hash(ref.s), row))
+            ref_out[q] = out
+            del ref
+        finally:
+            events.put(None)
+
+    threads = [threading.Thread(target=run_oracle, args=(c,)) for c in cfgs]
+    for th in threads:
+        th.start()
+    got = {}
+    for cfg in cfgs:
+        L, q = cfg["L"], cfg["q"]
+        live(f"L={L} q={q} cold start: 2 sweeps on the GPU")
+        lat = binding.Lattice(L, q, cfg["K"], seed=cfg["seed"], random_start=cfg["random_start"], obs_capacity=4)
+        res = []
+        for t in range(2):
+            lat.sweep(1)
+            res.append((_spin_hash(lat.spins()), lat.measure(t, 1)[0]))
+        got[q] = res
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+        live(f"L={L} q={q}: GPU done")
+    finished = 0
+    while finished < len(threads):
+        msg = events.get()   # each oracle step reports when it ends
+        if msg is None:
+            finished += 1
+        else:
+            live(msg)
+    for th in threads:
+        th.join()
+    for cfg in cfgs:
+        q = cfg["q"]
+        assert q in ref_out, f"the oracle for q={q} did not finish"
+        for t in range(2):
+            assert got[q][t][0] == ref_out[q][t][0], f"q={q}: spins differ after sweep {t}"
+            assert np.array_equal(got[q][t][1], ref_out[q][t][1]), f"q={q}: observables of sweep {t}"
+        live(f"q={q}: spins and observables bit-identical after 2 sweeps")
