@@ -81,9 +81,29 @@ def cpu_baseline(cfg: dict) -> dict:
     t0 = time.perf_counter()
     lat.run(1)
     dt = time.perf_counter() - t0
+    cpu = host_cpu()
     return {"value": L * L / (dt * 1e9), "unit": "spin flips/ns", "cores": 1, "kind": "oracle",
             "sample": f"1 sweep of the same L={L} q={cfg['q']} lattice from its start (sweep 0), "
-                      f"{dt:.1f} s on 1 host core ({os.cpu_count()} visible)"}
+                      f"{dt:.1f} s on 1 host core ({cpu['nproc']} available)",
+            "cpu_model": cpu["cpu_model"], "nproc": cpu["nproc"]}
+
+
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": cores}
 
 
 def copy_calibration(nbytes: int = 1 << 30):
@@ -96,6 +116,88 @@ def copy_calibration(nbytes: int = 1 << 30):
     b.copy_(a)
     torch.cuda.synchronize()
     del a, b
+
+
+def copy_ceiling(nbytes: int = 1 << 30, reps: int = 10) -> dict:
+    """The HBM rate a plain device-to-device copy reaches (read + write bytes
+    per second), timed with HIP events: the practical ceiling next to the 8 TB/s
+    peak."""
+    import torch
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_per_copy": 2 * nbytes, "ms": ms, "GB_per_s": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
+def huge_lattices(warmup: int, steps: int) -> dict:
+    """L = 65536 (2^32 sites, one lattice of ~23 GiB) from the cold start, q = 2
+    and q = 3 at K_c: flips/ns over `steps` sweeps after `warmup`, with the
+    per-kernel HIP-event times and the roofline fraction of the labelling kernel."""
+    import torch
+    from paper_1208_2080_amd import binding
+    out = {}
+    for name in ("L65536q2", "L65536q3"):
+        cfg = workloads()[name]
+        L, q = cfg["L"], cfg["q"]
+        N = L * L
+        print(f"# {name}: L={L} q={q} cold start, {warmup} + {steps} sweeps", file=sys.stderr, flush=True)
+        lat = binding.Lattice(L, q, cfg["K"], seed=cfg["seed"], random_start=cfg["random_start"], obs_capacity=64)
+        lat.sweep(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ph = lat.sweep_profiled(steps)
+        wall = time.perf_counter() - t0
+        obs = lat.measure(lat.sweeps_done - 1, 1)[0]
+        assert obs[2:].sum() == N, "observable counts do not sum to N"
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+        per = {PHASE_KERNELS[i]: ph[i] / steps for i in range(3)}
+        bl = KERNEL_BYTES_PER_SITE["k_bond_label"] * N / (per["k_bond_label"] * 1e-3) / 1e9
+        value = N * steps / (wall * 1e9)
+        out[name] = {"L": L, "q": q, "K": cfg["K"], "start": "cold", "warmup": warmup, "steps": steps,
+                     "flips_per_ns": value, "phase_ms_per_sweep": per,
+                     "k_bond_label_GB_per_s": bl, "k_bond_label_frac": bl / HBM_PEAK_GBS,
+                     "k_bond_label_traffic": measured_traffic("k_bond_label", name, 64),
+                     "sweep_roofline_frac": value * SWEEP_BYTES_PER_SITE / HBM_PEAK_GBS}
+    return out
+
+
+def _oracle_replica(args):
+    import oracle
+    r, sweeps = args
+    lat = oracle.OracleLattice(r["L"], r["q"], r["K"], r["seed"], random_start=r.get("random_start", True))
+    t0 = time.perf_counter()
+    lat.run(sweeps)
+    return r["L"] ** 2 * sweeps, time.perf_counter() - t0
+
+
+def cpu_baseline_batched(n_replicas: int, sweeps: int) -> dict:
+    """The oracle on the batched mix over all host cores, one replica per
+    process: aggregate flips/ns over the wall time of the pool."""
+    import multiprocessing as mp
+    from paper_1208_2080_amd import workloads as wl
+    reps = wl.batched_replicas(n=n_replicas, sweeps=sweeps)
+    cores = min(host_cpu()["nproc"], 16)
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(cores) as pool:
+        res = pool.map(_oracle_replica, [(r, sweeps) for r in reps], chunksize=1)
+    wall = time.perf_counter() - t0
+    flips = sum(f for f, _ in res)
+    return {"value": flips / (wall * 1e9), "unit": "spin flips/ns", "cores": cores, "kind": "oracle",
+            "sample": f"{sweeps} sweep(s) of each of the {n_replicas} batched replicas (one per process), "
+                      f"{wall:.1f} s wall"}
 
 
 def batched_vs_plain(n_replicas: int, sweeps: int, tile_rows: int) -> dict:
@@ -199,8 +301,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (reference for HBM byte counters)")
-    ap.add_argument("--batched", type=int, default=0, metavar="SWEEPS",
-                    help="also time 256 uneven replicas batched vs one after another for SWEEPS sweeps")
+    ap.add_argument("--batched", type=int, default=20, metavar="SWEEPS",
+                    help="time 256 uneven replicas batched vs one after another for SWEEPS sweeps (0: skip)")
+    ap.add_argument("--huge", type=int, default=10, metavar="SWEEPS",
+                    help="time SWEEPS sweeps of the L = 65536 lattices, q = 2 and 3 (0: skip)")
     ap.add_argument("--serve", type=int, default=0, metavar="JOBS",
                     help="also run the server on JOBS Poisson jobs at 0.5, 0.9 and 1.2 x capacity")
     ap.add_argument("--label-equivalence", type=int, default=0, metavar="SWEEPS",
@@ -300,14 +404,20 @@ def main():
         lat.close()
         del lat
         torch.cuda.empty_cache()
+    if args.huge:
+        out["L65536"] = huge_lattices(2, args.huge)
     if args.serve:
         out["serving"] = serving(args.serve, value, args.tile_rows)
     if args.batched:
         print("# batched vs plain", file=sys.stderr, flush=True)
         out["batched_vs_plain"] = batched_vs_plain(256, args.batched, args.tile_rows)
+    out["copy_ceiling"] = copy_ceiling()
     if not args.no_cpu_baseline:
         print("# timing the CPU oracle on one sweep", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(cfg)
+        if args.batched:
+            print("# timing the CPU oracle on the batched mix, all cores", file=sys.stderr, flush=True)
+            out["cpu_baseline_batched"] = cpu_baseline_batched(256, 1)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
