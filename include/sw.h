@@ -61,8 +61,12 @@ typedef struct sw_params {
     uint32_t obs_capacity; /* sweeps of observables kept in the device ring;
                               0 = no measurement ("update only"), else >= 2 */
     uint32_t tile_rows;    /* labelling tile height: 0 (default), 32, 64 or 128 */
-    uint32_t reserved;     /* must be 0 */
+    uint32_t flags;        /* 0, or SW_CLUSTER_SUMS */
 } sw_params;
+
+/* flags: also measure, for every sweep, the cluster-size sums of the sweep's
+ * clusters (sw_cluster_sums).  Needs L <= 32768 and obs_capacity > 0. */
+#define SW_CLUSTER_SUMS 1u
 
 typedef struct sw_lattice sw_lattice;
 typedef struct sw_batch sw_batch;
@@ -97,6 +101,17 @@ int sw_sweep(sw_lattice* h, uint32_t n_sweeps);
  * c.  Only the last obs_capacity sweeps since sw_init / sw_load_spins are
  * kept.  Synchronises the stream. */
 int sw_measure(sw_lattice* h, uint32_t first, uint32_t n, int64_t* host_out);
+
+/* Cluster-size sums of sweeps first .. first+n-1 (lattices made with
+ * SW_CLUSTER_SUMS), for the improved estimators of the moments of the
+ * magnetisation behind the moment ratio of Sec. 4: given a sweep's clusters C,
+ * the mean over their independent uniform new states of |M|^2 (M the simplex-
+ * vector magnetisation, the Ising M for q = 2) is S2 = sum_C |C|^2, and that
+ * of |M|^4 is (1 + 2/(q-1)) S2^2 - (2/(q-1)) S4 with S4 = sum_C |C|^4.
+ * host_out: n rows of 3 uint64: S2, then S4 as 128 bits (low word, high
+ * word).  Same availability rules as sw_measure (SW_ESTATE also without the
+ * flag).  Synchronises the stream. */
+int sw_cluster_sums(sw_lattice* h, uint32_t first, uint32_t n, uint64_t* host_out);
 
 /* sw_sweep with timing: HIP events are recorded on the handle's stream around
  * every kernel launch; the call then synchronises and writes the summed device
@@ -177,10 +192,11 @@ int sw_batch_sweep(sw_batch* b, const uint32_t* n_sweeps);
  * are launched directly.  Asynchronous. */
 int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps);
 
-/* sw_measure, sw_read_spins, sw_sweeps_done and sw_destroy for one replica
- * (replica >= n: SW_EINVAL). */
+/* sw_measure, sw_read_spins, sw_cluster_sums, sw_sweeps_done and sw_destroy
+ * for one replica (replica >= n: SW_EINVAL). */
 int sw_batch_measure(sw_batch* b, uint32_t replica, uint32_t first, uint32_t n, int64_t* host_out);
 int sw_batch_read_spins(sw_batch* b, uint32_t replica, uint8_t* host_out);
+int sw_batch_cluster_sums(sw_batch* b, uint32_t replica, uint32_t first, uint32_t n, uint64_t* host_out);
 int sw_batch_sweeps_done(const sw_batch* b, uint32_t replica, uint32_t* out);
 int sw_batch_destroy(sw_batch* b);
 

@@ -148,6 +148,16 @@ def derived(s: np.ndarray, q: int) -> dict:
     return d
 
 
+def cluster_sums(labels: np.ndarray):
+    """(S2, S4) = (sum over clusters of |C|^2, of |C|^4) as exact Python ints,
+    from cluster labels (each site's cluster root): the cluster sizes that the
+    improved estimators of the moments of the magnetisation use (the moment
+    ratio of Sec. 4)."""
+    sizes = np.bincount(np.asarray(labels, dtype=np.int64).reshape(-1))
+    sizes = [int(c) for c in sizes if c]
+    return sum(c * c for c in sizes), sum(c ** 4 for c in sizes)
+
+
 def label(bx: np.ndarray, by: np.ndarray) -> np.ndarray:
     """Minimum-site-index cluster labels of the graph of active bonds."""
     L = bx.shape[0]

@@ -28,7 +28,10 @@ class SwError(RuntimeError):
 class SwParams(ctypes.Structure):
     _fields_ = [("L", ctypes.c_uint32), ("q", ctypes.c_uint32), ("K", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("init", ctypes.c_uint32), ("obs_capacity", ctypes.c_uint32),
-                ("tile_rows", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("tile_rows", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+SW_CLUSTER_SUMS = 1
 
 
 # (name, restype, argtypes) of every function declared in include/sw.h
@@ -41,6 +44,7 @@ SIGNATURES = [
     ("sw_init", ctypes.c_int, [_PP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
     ("sw_sweep", ctypes.c_int, [_VP, _U32]),
     ("sw_measure", ctypes.c_int, [_VP, _U32, _U32, _VP]),
+    ("sw_cluster_sums", ctypes.c_int, [_VP, _U32, _U32, _VP]),
     ("sw_sweep_profiled", ctypes.c_int, [_VP, _U32, ctypes.POINTER(ctypes.c_double)]),
     ("sw_sweeps_done", ctypes.c_int, [_VP, ctypes.POINTER(_U32)]),
     ("sw_read_spins", ctypes.c_int, [_VP, _VP]),
@@ -56,6 +60,7 @@ SIGNATURES = [
     ("sw_batch_sweep_all", ctypes.c_int, [_VP, _U32]),
     ("sw_batch_measure", ctypes.c_int, [_VP, _U32, _U32, _U32, _VP]),
     ("sw_batch_read_spins", ctypes.c_int, [_VP, _U32, _VP]),
+    ("sw_batch_cluster_sums", ctypes.c_int, [_VP, _U32, _U32, _U32, _VP]),
     ("sw_batch_sweeps_done", ctypes.c_int, [_VP, _U32, ctypes.POINTER(_U32)]),
     ("sw_batch_destroy", ctypes.c_int, [_VP]),
     ("sw_batch_autotune", ctypes.c_int, [_PP, _U32, _VP, _U32, _U32, _VP, ctypes.c_size_t, _VP,
@@ -101,9 +106,18 @@ def _check(rc: int):
 
 
 def make_params(L: int, q: int, K: float, seed: int = 1, random_start: bool = True,
-                obs_capacity: int = 2, tile_rows: int = 0) -> SwParams:
+                obs_capacity: int = 2, tile_rows: int = 0, cluster_sums: bool = False) -> SwParams:
     return SwParams(int(L), int(q), float(K), int(seed), 1 if random_start else 0, int(obs_capacity),
-                    int(tile_rows), 0)
+                    int(tile_rows), SW_CLUSTER_SUMS if cluster_sums else 0)
+
+
+def _cluster_rows(raw: np.ndarray) -> np.ndarray:
+    """[S2, S4 low, S4 high] uint64 rows -> object array of Python ints [S2, S4]."""
+    out = np.empty((raw.shape[0], 2), dtype=object)
+    for i, (s2, lo, hi) in enumerate(raw.tolist()):
+        out[i, 0] = int(s2)
+        out[i, 1] = (int(hi) << 64) | int(lo)
+    return out
 
 
 def threshold(K: float) -> int:
@@ -142,10 +156,10 @@ class Lattice:
     """One L x L lattice resident on the GPU, swept by the HIP kernels."""
 
     def __init__(self, L: int, q: int, K: float, seed: int = 1, random_start: bool = True,
-                 obs_capacity: int = 1024, tile_rows: int = 0, device=None, stream=None):
+                 obs_capacity: int = 1024, tile_rows: int = 0, device=None, stream=None, cluster_sums=False):
         self.L, self.q, self.K, self.seed = int(L), int(q), float(K), int(seed)
         self.obs_capacity = int(obs_capacity)
-        self.params = make_params(L, q, K, seed, random_start, obs_capacity, tile_rows)
+        self.params = make_params(L, q, K, seed, random_start, obs_capacity, tile_rows, cluster_sums)
         nbytes = lib().sw_workspace_bytes(ctypes.byref(self.params))
         if nbytes == 0:
             raise SwError(SW_EINVAL, lib().sw_last_error().decode())
@@ -184,6 +198,13 @@ class Lattice:
         out = np.zeros((n, 2 + self.q), dtype=np.int64)
         _check(lib().sw_measure(self._h, int(first), int(n), out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+    def cluster_sums(self, first: int, n: int) -> np.ndarray:
+        """[S2, S4] per sweep (Python ints): sums over the sweep's clusters of
+        |C|^2 and |C|^4 (lattices made with cluster_sums=True)."""
+        raw = np.zeros((n, 3), dtype=np.uint64)
+        _check(lib().sw_cluster_sums(self._h, int(first), int(n), raw.ctypes.data_as(ctypes.c_void_p)))
+        return _cluster_rows(raw)
 
     def spins(self) -> np.ndarray:
         out = np.empty((self.L, self.L), dtype=np.uint8)
@@ -235,7 +256,7 @@ def _replica_params(replicas, obs_capacity: int, tile_rows: int):
     arr = (SwParams * len(replicas))()
     for i, r in enumerate(replicas):
         arr[i] = make_params(r["L"], r["q"], r["K"], r["seed"], r.get("random_start", True),
-                             r.get("obs_capacity", obs_capacity), tile_rows)
+                             r.get("obs_capacity", obs_capacity), tile_rows, r.get("cluster_sums", False))
     return arr
 
 
@@ -312,6 +333,11 @@ class Batch:
         out = np.zeros((n, 2 + q), dtype=np.int64)
         _check(lib().sw_batch_measure(self._h, int(r), int(first), int(n), out.ctypes.data_as(ctypes.c_void_p)))
         return out
+
+    def cluster_sums(self, r: int, first: int, n: int) -> np.ndarray:
+        raw = np.zeros((n, 3), dtype=np.uint64)
+        _check(lib().sw_batch_cluster_sums(self._h, int(r), int(first), int(n), raw.ctypes.data_as(ctypes.c_void_p)))
+        return _cluster_rows(raw)
 
     def spins(self, r: int) -> np.ndarray:
         L = self.replicas[r]["L"]

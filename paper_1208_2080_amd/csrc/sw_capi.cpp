@@ -51,6 +51,7 @@ struct Geometry {
     uint32_t L, q, W, ty, ntx, nty, ntiles, cap;
     size_t N;
     uint64_t thr;
+    bool csum;   // cluster-size sums measured
 };
 
 uint64_t threshold_of(double K)
@@ -71,7 +72,9 @@ int check_params(const sw_params* p, Geometry* g)
     if (p->obs_capacity > (1u << 28)) return fail(SW_EINVAL, "obs_capacity too large");
     const uint32_t ty = p->tile_rows ? p->tile_rows : DEFAULT_TY;
     if (ty != 32 && ty != 64 && ty != 128) return fail(SW_EINVAL, "tile_rows must be 0, 32, 64 or 128");
-    if (p->reserved != 0) return fail(SW_EINVAL, "reserved must be 0");
+    if (p->flags & ~SW_CLUSTER_SUMS) return fail(SW_EINVAL, "unknown flags 0x%x", p->flags);
+    if ((p->flags & SW_CLUSTER_SUMS) && (p->L > 32768 || p->obs_capacity == 0))
+        return fail(SW_EINVAL, "cluster sums need L <= 32768 and obs_capacity > 0");
     g->L = p->L;
     g->q = p->q;
     g->W = (p->L + 63) / 64;
@@ -82,6 +85,7 @@ int check_params(const sw_params* p, Geometry* g)
     g->cap = p->obs_capacity;
     g->N = (size_t)p->L * p->L;
     g->thr = threshold_of(p->K);
+    g->csum = (p->flags & SW_CLUSTER_SUMS) != 0;
     return SW_OK;
 }
 
@@ -91,7 +95,7 @@ inline uint32_t ring_slots(const Geometry& g) { return g.cap ? g.cap + 1 : 0; }
 
 // Byte offsets of one lattice's arrays inside its slice of the workspace.
 struct Carve {
-    size_t state, desc, spins, lab, bonds, edges, nodes, ring, obs, total;
+    size_t state, desc, spins, lab, bonds, edges, nodes, csize, ring, obs, total;
 };
 
 Carve carve(const Geometry& g)
@@ -110,8 +114,9 @@ Carve carve(const Geometry& g)
     c.bonds = take((size_t)g.ntiles * 2 * g.ty * 8);
     c.edges = take((size_t)g.ntiles * edge_words(g.ty) * 4);
     c.nodes = take((size_t)g.ntiles * nslot(g.ty) * 8);
+    c.csize = take(g.csum ? (size_t)g.ntiles * nslot(g.ty) * 8 : 0);
     c.ring = take((size_t)ring_slots(g) * NCOPY * ring_stride(g.q) * 8);
-    c.obs = take((size_t)ring_slots(g) * (g.q + 1) * 8);
+    c.obs = take((size_t)ring_slots(g) * ring_words(g.q) * 8);
     c.total = off;
     return c;
 }
@@ -145,6 +150,7 @@ LatDesc make_desc(const Geometry& g, const sw_params* p, char* base, const Carve
     d.bonds = reinterpret_cast<uint64_t*>(base + c.bonds);
     d.edges = reinterpret_cast<uint32_t*>(base + c.edges);
     d.nodes = reinterpret_cast<uint64_t*>(base + c.nodes);
+    d.csize = g.csum ? reinterpret_cast<uint64_t*>(base + c.csize) : nullptr;
     d.ring = g.cap ? reinterpret_cast<int64_t*>(base + c.ring) : nullptr;
     d.obs = g.cap ? reinterpret_cast<int64_t*>(base + c.obs) : nullptr;
     d.counter = &st->counter;
@@ -199,15 +205,23 @@ int check_device_error(const LatDesc& d, hipStream_t s)
 // n_0..n_{q-1}.  A small kernel sums each record's NCOPY partial copies into
 // the lattice's staging area, so only (q + 1) words per sweep cross to the
 // host, in one copy and one synchronisation; n_0 = N - the other counts.
-int read_ring(const LatDesc& d, size_t N, hipStream_t s, uint32_t first, uint32_t n, int64_t* out)
+// With cs_out (n rows of 3 uint64): the cluster-size sums of the records,
+// sum |C|^2 and the low and high words of sum |C|^4, instead of the rows.
+int read_ring(const LatDesc& d, size_t N, hipStream_t s, uint32_t first, uint32_t n, int64_t* out,
+              uint64_t* cs_out = nullptr)
 {
     if (n == 0) return SW_OK;
     if (n >= d.cap) return fail(SW_ESTATE, "internal: %u records exceed the ring", n);
-    const uint32_t W = d.q + 1;
+    const uint32_t W = ring_words(d.q);
     std::vector<int64_t> buf((size_t)n * W);
     HIP_TRY(launch_ring_sum(d.ring, d.obs, d.cap, first % d.cap, n, d.q, s));
     HIP_TRY(hipMemcpyAsync(buf.data(), d.obs, buf.size() * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (cs_out) {
+        for (uint32_t k = 0; k < n; ++k)
+            for (uint32_t j = 0; j < 3; ++j) cs_out[(size_t)k * 3 + j] = (uint64_t)buf[(size_t)k * W + cs_word(d.q) + j];
+        return SW_OK;
+    }
     for (uint32_t k = 0; k < n; ++k) {
         const int64_t* r = buf.data() + (size_t)k * W;
         int64_t* row = out + (size_t)k * (2 + d.q);
@@ -235,6 +249,7 @@ int enqueue_sweeps(const Work& w, uint32_t n, bool measure, const LatDesc* descs
         HIP_TRY(launch_merge(w));
         if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 2], w.stream));
         HIP_TRY(launch_flip(w, k));
+        if (w.cluster) HIP_TRY(launch_cluster_sums(w, k));
         if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 3], w.stream));
     }
     if (measure) HIP_TRY(launch_measure(w, n - 1));
@@ -292,6 +307,7 @@ int sw_init(const sw_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
         HIP_TRY(hipMemsetAsync(h->base + c.state, 0, sizeof(DevState), h->stream));
         HIP_TRY(hipMemcpyAsync(h->d_desc, &h->desc, sizeof(LatDesc), hipMemcpyHostToDevice, h->stream));
         if (g.cap) HIP_TRY(hipMemsetAsync(h->base + c.ring, 0, (size_t)ring_slots(g) * NCOPY * ring_stride(g.q) * 8, h->stream));
+        if (g.csum) HIP_TRY(hipMemsetAsync(h->base + c.csize, 0, (size_t)g.ntiles * nslot(g.ty) * 8, h->stream));
         if (p->init) HIP_TRY(launch_init(h->d_desc, 0, g.N, 1u, h->stream));
         else HIP_TRY(hipMemsetAsync(h->desc.s, 0, g.N, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
@@ -311,7 +327,7 @@ int sw_sweep(sw_lattice* h, uint32_t n_sweeps)
     if (!h) return fail(SW_EINVAL, "handle is NULL");
     if (n_sweeps == 0) return SW_OK;
     if ((uint64_t)h->done + n_sweeps > 0xFFFFFFFFull) return fail(SW_ESTATE, "sweep counter would overflow");
-    const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream};
+    const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream, h->g.csum};
     const int rc = enqueue_sweeps(w, n_sweeps, h->g.cap != 0, h->d_desc, 1, nullptr);
     if (rc) return rc;
     h->done += n_sweeps;
@@ -335,7 +351,7 @@ int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms)
             rc = fail(SW_EHIP, "hipEventCreate failed");
             break;
         }
-    const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream};
+    const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream, h->g.csum};
     if (rc == SW_OK) rc = enqueue_sweeps(w, n_sweeps, h->g.cap != 0, h->d_desc, 1, nullptr, ev.data());
     if (rc == SW_OK) {
         h->done += n_sweeps;
@@ -384,6 +400,20 @@ int sw_measure(sw_lattice* h, uint32_t first, uint32_t n, int64_t* host_out)
     int rc = check_device_error(h->desc, h->stream);
     if (rc) return rc;
     return read_ring(h->desc, h->g.N, h->stream, first, n, host_out);
+}
+
+int sw_cluster_sums(sw_lattice* h, uint32_t first, uint32_t n, uint64_t* host_out)
+{
+    if (!h || (!host_out && n)) return fail(SW_EINVAL, "NULL argument");
+    if (!h->g.csum) return fail(SW_ESTATE, "lattice was created without SW_CLUSTER_SUMS");
+    const uint64_t end = (uint64_t)first + n;
+    const uint64_t lo = std::max<uint64_t>(h->first_obs, h->done > h->g.cap ? h->done - h->g.cap : 0);
+    if (first < lo || end > h->done)
+        return fail(SW_ESTATE, "sweeps [%u, %llu) not available (have [%llu, %u))", first,
+                    (unsigned long long)end, (unsigned long long)lo, h->done);
+    int rc = check_device_error(h->desc, h->stream);
+    if (rc) return rc;
+    return read_ring(h->desc, h->g.N, h->stream, first, n, nullptr, host_out);
 }
 
 int sw_read_spins(sw_lattice* h, uint8_t* host_out)
@@ -531,6 +561,7 @@ struct sw_batch {
     std::vector<uint32_t> h_n;
     std::vector<uint32_t> map_order;  // replica order of the uploaded map
     std::map<uint32_t, hipGraphExec_t> graphs;   // sweep_all graphs by sweep count
+    bool csum = false;                           // some replica measures cluster-size sums
 };
 
 // sweep_all graphs kept per batch (one per distinct sweep count)
@@ -627,10 +658,11 @@ int batch_enqueue(sw_batch* b, const uint32_t* n_each)
     b->h_n.assign(n_each, n_each + b->n);
     HIP_TRY(hipMemcpyAsync(b->d_n, b->h_n.data(), b->n * sizeof(uint32_t), hipMemcpyHostToDevice, b->stream));
     for (uint32_t k = 0; k < kmax; ++k) {
-        const Work w{b->d_descs, b->d_map, prefix[k], b->ty, b->stream};
+        const Work w{b->d_descs, b->d_map, prefix[k], b->ty, b->stream, b->csum};
         HIP_TRY(launch_bond_label(w, k, k > 0 ? 1u : 0u));
         HIP_TRY(launch_merge(w));
         HIP_TRY(launch_flip(w, k));
+        if (w.cluster) HIP_TRY(launch_cluster_sums(w, k));
     }
     const Work w0{b->d_descs, b->d_map, prefix[0], b->ty, b->stream};
     HIP_TRY(launch_measure_each(w0, b->d_n));
@@ -687,6 +719,7 @@ int sw_batch_init(const sw_params* params, uint32_t n, void* dev_ws, size_t ws_b
     b->d_map = reinterpret_cast<WorkItem*>(b->base + lay.map);
     b->d_n = reinterpret_cast<uint32_t*>(b->base + lay.nvec);
     b->desc.resize(n);
+    for (uint32_t r = 0; r < n; ++r) b->csum = b->csum || b->g[r].csum;
     for (uint32_t r = 0; r < n; ++r) {
         b->desc[r] = make_desc(b->g[r], &params[r], b->base + b->off[r], b->c[r]);
         if (!division_ok(b->g[r].L, b->desc[r].magic, b->desc[r].shift)) {
@@ -702,6 +735,9 @@ int sw_batch_init(const sw_params* params, uint32_t n, void* dev_ws, size_t ws_b
             if (b->g[r].cap)
                 HIP_TRY(hipMemsetAsync(base + b->c[r].ring, 0,
                                        (size_t)ring_slots(b->g[r]) * NCOPY * ring_stride(b->g[r].q) * 8, b->stream));
+            if (b->g[r].csum)
+                HIP_TRY(hipMemsetAsync(base + b->c[r].csize, 0, (size_t)b->g[r].ntiles * nslot(b->g[r].ty) * 8,
+                                       b->stream));
             if (params[r].init) HIP_TRY(launch_init(b->d_descs, r, b->g[r].N, 1u, b->stream));
             else HIP_TRY(hipMemsetAsync(b->desc[r].s, 0, b->g[r].N, b->stream));
         }
@@ -766,9 +802,9 @@ int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps)
         HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
         int rc = SW_OK;
         for (uint32_t k = 0; k < n_sweeps && rc == SW_OK; ++k) {
-            const Work w{b->d_descs, b->d_map, M, b->ty, b->stream};
+            const Work w{b->d_descs, b->d_map, M, b->ty, b->stream, b->csum};
             if (launch_bond_label(w, k, k > 0 ? 1u : 0u) != hipSuccess || launch_merge(w) != hipSuccess ||
-                launch_flip(w, k) != hipSuccess)
+                launch_flip(w, k) != hipSuccess || (w.cluster && launch_cluster_sums(w, k) != hipSuccess))
                 rc = SW_EHIP;
         }
         if (rc == SW_OK) {
@@ -806,6 +842,22 @@ int sw_batch_measure(sw_batch* b, uint32_t replica, uint32_t first, uint32_t n, 
     rc = check_device_error(b->desc[replica], b->stream);
     if (rc) return rc;
     return read_ring(b->desc[replica], g.N, b->stream, first, n, host_out);
+}
+
+int sw_batch_cluster_sums(sw_batch* b, uint32_t replica, uint32_t first, uint32_t n, uint64_t* host_out)
+{
+    int rc = batch_check(b, replica);
+    if (rc) return rc;
+    if (!host_out && n) return fail(SW_EINVAL, "host_out is NULL");
+    const Geometry& g = b->g[replica];
+    if (!g.csum) return fail(SW_ESTATE, "replica %u was created without SW_CLUSTER_SUMS", replica);
+    const uint64_t end = (uint64_t)first + n;
+    const uint32_t done = b->done[replica];
+    const uint64_t lo = std::max<uint64_t>(b->first_obs[replica], done > g.cap ? done - g.cap : 0);
+    if (first < lo || end > done) return fail(SW_ESTATE, "sweeps [%u, %llu) not available", first, (unsigned long long)end);
+    rc = check_device_error(b->desc[replica], b->stream);
+    if (rc) return rc;
+    return read_ring(b->desc[replica], g.N, b->stream, first, n, nullptr, host_out);
 }
 
 int sw_batch_read_spins(sw_batch* b, uint32_t replica, uint8_t* host_out)
@@ -998,6 +1050,8 @@ int sw_group_sweep(sw_group* g, sw_lattice* const* lats, const uint32_t* n_sweep
         if (n_sweeps[i]) tiles += h->g.ntiles;
         kmax = std::max(kmax, n_sweeps[i]);
     }
+    bool csum = false;
+    for (uint32_t i = 0; i < n; ++i) csum = csum || (n_sweeps[i] && lats[i]->g.csum);
     if (tiles > g->max_tiles) return fail(SW_EINVAL, "%llu tiles exceed the group's %llu",
                                           (unsigned long long)tiles, (unsigned long long)g->max_tiles);
     if (kmax == 0) return SW_OK;
@@ -1023,10 +1077,11 @@ int sw_group_sweep(sw_group* g, sw_lattice* const* lats, const uint32_t* n_sweep
     size_t pos = order.size();
     for (uint32_t k = 0; k < kmax; ++k) {
         while (pos > 0 && n_sweeps[order[pos - 1]] <= k) --pos;
-        const Work w{g->d_descs, g->d_map, pos ? ends[pos - 1] : 0u, g->ty, g->stream};
+        const Work w{g->d_descs, g->d_map, pos ? ends[pos - 1] : 0u, g->ty, g->stream, csum};
         HIP_TRY(launch_bond_label(w, k, k > 0 ? 1u : 0u));
         HIP_TRY(launch_merge(w));
         HIP_TRY(launch_flip(w, k));
+        if (w.cluster) HIP_TRY(launch_cluster_sums(w, k));
     }
     const Work w0{g->d_descs, g->d_map, ends.back(), g->ty, g->stream};
     HIP_TRY(launch_measure_each(w0, g->d_n));
@@ -1120,6 +1175,7 @@ extern "C" int sw_sweep_static(const sw_params* p, uint8_t* dev_spins, uint32_t 
     int rc = check_params(p, &g);
     if (rc) return rc;
     if (!dev_spins) return fail(SW_EINVAL, "dev_spins is NULL");
+    if (g.csum) return fail(SW_EINVAL, "cluster sums are not measured by this entry point");
     if ((uint64_t)first_sweep + n_sweeps > 0xFFFFFFFFull) return fail(SW_ESTATE, "sweep counter would overflow");
     const bool measure = dev_obs != nullptr;
     const StaticCarve c = carve_static(g, measure);

@@ -1012,6 +1012,137 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
 }
 
 // ---------------------------------------------------------------------------
+// Cluster-size sums of a sweep's clusters, for the improved estimators of the
+// moments of the magnetisation (given the clusters, the mean of |M|^2 over the
+// clusters' independent uniform states is sum |C|^2, and that of |M|^4 a
+// combination of (sum |C|^2)^2 and sum |C|^4).  After the flip the labels and
+// the edge forest still describe the sweep's clusters.  k_csize: one workgroup
+// per tile counts the sites of each tile-local cluster in LDS; a cluster
+// inside the tile adds |C|^2 and |C|^4 at once, the others add their count to
+// their edge-forest root.  k_croot: every edge-forest root adds the square and
+// fourth power of its gathered size and clears it.  |C| <= 2^30, so |C|^2 fits
+// 64 bits and the sums of |C|^4 take 128 (two words, carried by hand).
+
+// v added to the 128-bit number (lo, hi), atomically.
+template <class P>
+__device__ __forceinline__ void add_u128(P lo, P hi, unsigned __int128 v, int scope)
+{
+    const uint64_t vl = (uint64_t)v, vh = (uint64_t)(v >> 64);
+    if (!vl && !vh) return;
+    uint64_t old = 0;
+    if (scope == __HIP_MEMORY_SCOPE_AGENT)
+        old = __hip_atomic_fetch_add(lo, (unsigned long long)vl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        old = __hip_atomic_fetch_add(lo, (unsigned long long)vl, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint64_t up = vh + ((old + vl) < old ? 1u : 0u);
+    if (!up) return;
+    if (scope == __HIP_MEMORY_SCOPE_AGENT)
+        __hip_atomic_fetch_add(hi, (unsigned long long)up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else
+        __hip_atomic_fetch_add(hi, (unsigned long long)up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// The workgroup's sums (in LDS) into ring record t, partial copy 0.
+__device__ __forceinline__ void cs_flush(const LatDesc& d, uint32_t t, unsigned long long* sums, uint32_t tid)
+{
+    if (tid != 0 || !d.cap) return;
+    const gptr<unsigned long long> rec =
+        (gptr<unsigned long long>)(glb(d.ring) + (size_t)(t % d.cap) * NCOPY * ring_stride(d.q) + cs_word(d.q));
+    if (sums[0]) __hip_atomic_fetch_add(rec, sums[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    add_u128(rec + 1, rec + 2, ((unsigned __int128)sums[2] << 64) | sums[1], __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void cs_add(unsigned long long* sums, uint64_t c)
+{
+    const uint64_t c2 = c * c;
+    __hip_atomic_fetch_add(&sums[0], (unsigned long long)c2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    add_u128(&sums[1], &sums[2], (unsigned __int128)c2 * c2, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <int TY>
+__global__ __launch_bounds__(threads_of<TY>()) void k_csize(const LatDesc* descs, const WorkItem* map, uint32_t k)
+{
+    constexpr uint32_t NT = threads_of<TY>();
+    __shared__ uint16_t E[TY * TX];
+    __shared__ uint32_t C[TY * TX];
+    __shared__ unsigned long long sums[3];
+    LatDesc d;
+    uint32_t tile, lat;
+    if (!pick(descs, map, blockIdx.x, true, d, tile, lat)) return;
+    if (!d.csize) return;
+    const TileGeom g = tile_geom(d, tile, TY);
+    const uint32_t t = *glb(d.counter) + k;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t NS = nslot(TY), n_nodes = d.ntiles * NS, node0 = tile * NS;
+    const gptr<uint32_t> lab = glb(d.lab);
+    bool bad = false;
+    if (tid < 3) sums[tid] = 0;
+    for (uint32_t li = tid; li < TY * TX; li += NT) {
+        const uint32_t r = li / TX, c = li % TX;
+        const uint32_t v = (r < g.h && c < g.w) ? lab[(size_t)(g.y0 + r) * d.L + g.x0 + c] : (ROOT | NOSLOT);
+        E[li] = (v & ROOT) ? (ROOT16 | (v & 0x7FFFu)) : v;
+        C[li] = 0;
+    }
+    __syncthreads();
+    for (uint32_t li = tid; li < TY * TX; li += NT) {
+        if (li / TX >= g.h || li % TX >= g.w) continue;
+        uint32_t cur = li, x = E[cur];
+        while (!(x & ROOT16) && x < cur) {
+            cur = x;
+            x = E[cur];
+        }
+        if (!(x & ROOT16)) {
+            bad = true;
+            continue;
+        }
+        atomicAdd(&C[cur], 1u);
+    }
+    __syncthreads();
+    for (uint32_t li = tid; li < TY * TX; li += NT) {
+        const uint32_t x = E[li], c = C[li];
+        if (!(x & ROOT16) || !c) continue;
+        const uint32_t slot = x & 0x7FFFu;
+        if (slot == NOSLOT) {
+            cs_add(sums, c);
+        } else {
+            const uint64_t rw = n_root(glb(d.nodes), n_nodes, node0 + slot, bad);
+            if (!bad)
+                __hip_atomic_fetch_add((gptr<unsigned long long>)(glb(d.csize) + node_of(rw)), (unsigned long long)c,
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    __syncthreads();
+    cs_flush(d, t, sums, tid);
+    if (bad) flag_error(d.err);
+}
+
+template <int TY>
+__global__ __launch_bounds__(threads_of<TY>()) void k_croot(const LatDesc* descs, const WorkItem* map, uint32_t k)
+{
+    constexpr uint32_t NT = threads_of<TY>();
+    __shared__ unsigned long long sums[3];
+    LatDesc d;
+    uint32_t tile, lat;
+    if (!pick(descs, map, blockIdx.x, true, d, tile, lat)) return;
+    if (!d.csize) return;
+    const uint32_t t = *glb(d.counter) + k;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t NS = nslot(TY), node0 = tile * NS;
+    const uint32_t n_used = min(glb(d.edges)[(size_t)tile * edge_words(TY) + 6], NS);
+    if (tid < 3) sums[tid] = 0;
+    __syncthreads();
+    for (uint32_t s = tid; s < n_used; s += NT) {
+        const uint32_t node = node0 + s;
+        if (node_of(glb(d.nodes)[node]) != node) continue;   // not a root
+        const uint64_t c = glb(d.csize)[node];
+        glb(d.csize)[node] = 0;
+        if (c) cs_add(sums, c);
+    }
+    __syncthreads();
+    cs_flush(d, t, sums, tid);
+}
+
+// ---------------------------------------------------------------------------
 // Measurement of the current configuration into the ring record of sweep
 // counter + k (used after the last sweep of a call).
 template <int TY>
@@ -1125,7 +1256,7 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_resolve(const LatDesc* des
 __global__ __launch_bounds__(256) void k_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, uint32_t slot0,
                                                   uint32_t n, uint32_t q)
 {
-    const uint32_t W = q + 1;
+    const uint32_t W = ring_words(q);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * W) return;
     const uint32_t rec = i / W, w = i - rec * W;
@@ -1236,6 +1367,14 @@ hipError_t launch_flip(const Work& w, uint32_t k)
     return hipGetLastError();
 }
 
+hipError_t launch_cluster_sums(const Work& w, uint32_t k)
+{
+    if (w.nitems == 0) return hipSuccess;
+    SWMI_TY_DISPATCH(w.ty, k_csize, w.nitems, w.descs, w.map, k);
+    SWMI_TY_DISPATCH(w.ty, k_croot, w.nitems, w.descs, w.map, k);
+    return hipGetLastError();
+}
+
 hipError_t launch_measure(const Work& w, uint32_t k)
 {
     if (w.nitems == 0) return hipSuccess;
@@ -1271,7 +1410,7 @@ hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, uint32_t ntiles, u
 hipError_t launch_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, uint32_t slot0, uint32_t n, uint32_t q,
                            hipStream_t s)
 {
-    const uint64_t total = (uint64_t)n * (q + 1);
+    const uint64_t total = (uint64_t)n * ring_words(q);
     if (total == 0) return hipSuccess;
     if (total > 0xFFFFFFFFull || slot0 >= slots || n >= slots) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_ring_sum, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, ring, out, slots, slot0, n, q);

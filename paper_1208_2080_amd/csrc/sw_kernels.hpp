@@ -17,12 +17,16 @@ struct Work {
     uint32_t nitems;
     uint32_t ty;
     hipStream_t stream;
+    bool cluster = false;  // some lattice measures cluster-size sums
 };
 
 hipError_t launch_bond_label(const Work& w, uint32_t k, uint32_t flags);
 hipError_t launch_merge(const Work& w);
 hipError_t launch_flip(const Work& w, uint32_t k);
 hipError_t launch_measure(const Work& w, uint32_t k);
+// cluster-size sums of the sweep counter + k (after its flip), for the
+// lattices that measure them
+hipError_t launch_cluster_sums(const Work& w, uint32_t k);
 // measurement after n_each[lattice] sweeps of each lattice (batched form)
 hipError_t launch_measure_each(const Work& w, const uint32_t* n_each);
 hipError_t launch_init(const LatDesc* descs, uint32_t lat, size_t N, uint32_t random_start, hipStream_t s);

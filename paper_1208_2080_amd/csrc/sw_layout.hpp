@@ -56,9 +56,15 @@ __host__ __device__ constexpr uint32_t edge_words(uint32_t ty) { return 8u + ty 
 // Nodes of a tile's edge forest: at most one per edge site.
 __host__ __device__ constexpr uint32_t nslot(uint32_t ty) { return 2u * TX + 2u * ty; }
 
-// int64 words between partial copies of a ring record: the q + 1 sums rounded
-// up to whole 256-byte blocks, so no two copies share a cache line.
-__host__ __device__ constexpr uint32_t ring_stride(uint32_t q) { return (q + 1u + 31u) & ~31u; }
+// Words of a ring record: n_unsat, n_active, n_1..n_{q-1} (q + 1 sums), then
+// the cluster-size sums of the sweep's clusters, sum |C|^2 and sum |C|^4 (the
+// latter 128 bits: low word, high word), kept in partial copy 0 only.
+__host__ __device__ constexpr uint32_t ring_words(uint32_t q) { return q + 4u; }
+__host__ __device__ constexpr uint32_t cs_word(uint32_t q) { return q + 1u; }
+
+// int64 words between partial copies of a ring record: the record rounded up
+// to whole 256-byte blocks, so no two copies share a cache line.
+__host__ __device__ constexpr uint32_t ring_stride(uint32_t q) { return (ring_words(q) + 31u) & ~31u; }
 
 struct DevState {
     uint32_t err;          // nonzero: a safety cap tripped
@@ -72,6 +78,7 @@ struct LatDesc {
     uint64_t* bonds;
     uint32_t* edges;
     uint64_t* nodes;       // edge forest, nslot(TY) words per tile
+    uint64_t* csize;       // cluster sizes gathered at edge-forest roots (null: no cluster sums)
     int64_t* ring;
     int64_t* obs;          // staging of summed ring records (reads only)
     uint32_t* counter;     // sweeps done

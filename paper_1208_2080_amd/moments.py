@@ -42,6 +42,26 @@ def m2_from_counts(counts: np.ndarray, q: int) -> np.ndarray:
     return acc / (q - 1)
 
 
+def improved_from_cluster_sums(cs_rows, N: int, q: int):
+    """Improved estimators of m^2 and m^4 per sweep from the cluster-size sums
+    [S2, S4] (exact integers) of the sweep's clusters: the means of |M|^2 / N^2
+    and |M|^4 / N^4 over the clusters' independent uniform states,
+
+        E|M|^2 = S2,   E|M|^4 = ((q + 1) S2^2 - 2 S4) / (q - 1),
+
+    (simplex-vector magnetisation: e(a).e(b) = 1 if a = b, -1/(q-1) else, so
+    cross terms of different clusters vanish on average and E (e(a).e(b))^2 =
+    1/(q-1)).  The numerators are exact integers; each ratio is rounded once."""
+    m2 = np.empty(len(cs_rows), dtype=np.float64)
+    m4 = np.empty(len(cs_rows), dtype=np.float64)
+    N2, N4 = N * N, N ** 4
+    for i, (s2, s4) in enumerate(cs_rows):
+        s2, s4 = int(s2), int(s4)
+        m2[i] = s2 / N2
+        m4[i] = ((q + 1) * s2 * s2 - 2 * s4) / ((q - 1) * N4)
+    return m2, m4
+
+
 def _jackknife(blocks_num: np.ndarray, blocks_den: np.ndarray):
     """Ratio <a> / <b>^2 and its jackknife error over equal blocks."""
     n = len(blocks_num)
@@ -61,7 +81,17 @@ def moments(rows: np.ndarray, q: int, n_blocks: int = 20) -> dict:
     observable rows [n_unsat, n_active, n_0, ..., n_{q-1}]."""
     rows = np.asarray(rows, dtype=np.int64)
     m2 = m2_from_counts(rows[:, 2:2 + q], q)
-    m4 = m2 * m2
+    return _block_moments(m2, m2 * m2, n_blocks)
+
+
+def improved_moments(cs_rows, N: int, q: int, n_blocks: int = 20) -> dict:
+    """As ``moments`` with the cluster-size improved estimators (cs_rows: the
+    [S2, S4] of each sweep)."""
+    m2, m4 = improved_from_cluster_sums(cs_rows, N, q)
+    return _block_moments(m2, m4, n_blocks)
+
+
+def _block_moments(m2: np.ndarray, m4: np.ndarray, n_blocks: int) -> dict:
     nb = max(1, min(n_blocks, len(m2)))
     per = len(m2) // nb
     b2 = m2[:nb * per].reshape(nb, per).mean(axis=1)
@@ -86,22 +116,25 @@ def crossing(Ks, U_small, U_large):
 
 
 def run(q: int, Ls, K_factors, sweeps: int, therm: int, chunk: int = 1000, seed0: int = 7000,
-        tile_rows=0, device=None) -> dict:
+        tile_rows=0, device=None, improved: bool = True) -> dict:
     """Sweep one replica per (L, K = K_c(q) * factor) in one batch on the GPU
     (random start; `therm` sweeps discarded, then `sweeps` measured) and return
-    U per replica and the crossings of successive sizes."""
+    U per replica and the crossings of successive sizes, from the state counts
+    and (improved=True) also from the cluster-size improved estimators."""
     import torch
     from . import binding
     from . import workloads as wl
 
     Kc = wl.critical_coupling(q)
     grid = [(int(L), float(f)) for L in Ls for f in K_factors]
-    reps = [{"L": L, "q": q, "K": Kc * f, "seed": seed0 + i, "random_start": True} for i, (L, f) in enumerate(grid)]
+    reps = [{"L": L, "q": q, "K": Kc * f, "seed": seed0 + i, "random_start": True, "cluster_sums": improved}
+            for i, (L, f) in enumerate(grid)]
     chunk = max(1, min(chunk, sweeps))
     b = binding.Batch(reps, obs_capacity=chunk + 1, tile_rows=tile_rows, device=device)
     if therm:
         b.sweep_all(therm)
     rows = [[] for _ in reps]
+    cs = [[] for _ in reps]
     t0 = time.perf_counter()
     done = 0
     while done < sweeps:
@@ -109,6 +142,8 @@ def run(q: int, Ls, K_factors, sweeps: int, therm: int, chunk: int = 1000, seed0
         b.sweep_all(n)
         for r in range(len(reps)):
             rows[r].append(b.measure(r, therm + done, n))
+            if improved:
+                cs[r].append(b.cluster_sums(r, therm + done, n))
         done += n
     torch.cuda.synchronize(b.device)
     wall = time.perf_counter() - t0
@@ -117,8 +152,11 @@ def run(q: int, Ls, K_factors, sweeps: int, therm: int, chunk: int = 1000, seed0
            "wall_s": wall, "flips_per_ns": flips / (wall * 1e9), "points": []}
     b.close()
     U = {}
-    for (L, f), rr in zip(grid, rows):
+    for (L, f), rr, cc in zip(grid, rows, cs):
         mo = moments(np.concatenate(rr), q)
+        if improved:
+            imp = improved_moments(np.concatenate(cc), L * L, q)
+            mo.update({k + "_impr": v for k, v in imp.items() if k != "samples"})
         U[(L, f)] = mo
         out["points"].append({"L": L, "K_over_Kc": f, **mo})
     Ls_sorted = sorted(set(L for L, _ in grid))
@@ -126,7 +164,10 @@ def run(q: int, Ls, K_factors, sweeps: int, therm: int, chunk: int = 1000, seed0
     out["crossings"] = []
     for La, Lb in zip(Ls_sorted, Ls_sorted[1:]):
         k = crossing(fs, [U[(La, f)]["U"] for f in fs], [U[(Lb, f)]["U"] for f in fs])
-        out["crossings"].append({"L": [La, Lb], "K_over_Kc": k})
+        c = {"L": [La, Lb], "K_over_Kc": k}
+        if improved:
+            c["K_over_Kc_impr"] = crossing(fs, [U[(La, f)]["U_impr"] for f in fs], [U[(Lb, f)]["U_impr"] for f in fs])
+        out["crossings"].append(c)
     return out
 
 

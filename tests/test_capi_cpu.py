@@ -67,6 +67,19 @@ def test_invalid_params_rejected(L, q, K, cap, ty):
     assert binding.lib().sw_last_error().decode() != ""
 
 
+def test_flags_are_checked():
+    p = binding.make_params(64, 2, 1.0, obs_capacity=4)
+    p.flags = 2                                   # unknown flag
+    assert binding.lib().sw_workspace_bytes(ctypes.byref(p)) == 0
+    for L, cap in [(40000, 4), (64, 0)]:          # cluster sums: L <= 32768 and a ring
+        p = binding.make_params(L, 2, 1.0, obs_capacity=cap, cluster_sums=True)
+        assert binding.lib().sw_workspace_bytes(ctypes.byref(p)) == 0
+    plain = binding.make_params(64, 2, 1.0, obs_capacity=4)
+    sums = binding.make_params(64, 2, 1.0, obs_capacity=4, cluster_sums=True)
+    # the cluster sums need one more word per edge-forest node
+    assert binding.lib().sw_workspace_bytes(ctypes.byref(sums)) > binding.lib().sw_workspace_bytes(ctypes.byref(plain))
+
+
 def test_init_rejects_bad_workspace_without_touching_the_gpu():
     lib = binding.lib()
     p = binding.make_params(16, 2, 1.0)

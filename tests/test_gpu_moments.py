@@ -65,3 +65,63 @@ def test_moment_ratios_cross_near_Kc():
     k = res["crossings"][0]["K_over_Kc"]
     say(f"crossing at K/K_c = {k}")
     assert k is not None and abs(k - 1.0) < 0.01
+
+
+def test_cluster_sums_equal_the_oracle_every_sweep():
+    """S2 = sum |C|^2 and S4 = sum |C|^4 of every sweep's clusters, bit for bit
+    against the oracle's labels: plain lattices of ragged sizes and every tile
+    height, multi-sweep calls, and a batch."""
+    import oracle
+    cases = [(2, 2, 1.5, 0), (17, 3, wl.critical_coupling(3), 0), (100, 2, wl.critical_coupling(2), 32),
+             (130, 4, wl.critical_coupling(4), 128), (257, 2, wl.critical_coupling(2), 64),
+             (64, 5, float("inf"), 0), (80, 2, 0.0, 0)]
+    for L, q, K, ty in cases:
+        say(f"cluster sums L={L} q={q} K={K} ty={ty}")
+        lat = binding.Lattice(L, q, K, seed=L + q, obs_capacity=16, tile_rows=ty, cluster_sums=True)
+        ref = oracle.OracleLattice(L, q, K, L + q)
+        want = []
+        for _ in range(6):
+            want.append(oracle.cluster_sums(ref.sweep()["labels"]))
+        lat.sweep(1)
+        lat.sweep(5)
+        got = lat.cluster_sums(0, 6)
+        assert [tuple(r) for r in got.tolist()] == want, (L, q, K, ty)
+        assert np.array_equal(lat.spins(), ref.s)
+        lat.close()
+    reps = [dict(L=L, q=q, K=K, seed=L + q, cluster_sums=True) for L, q, K, _ in cases]
+    b = binding.Batch(reps, obs_capacity=16)
+    b.sweep_all(3)
+    for r, (L, q, K, _) in enumerate(cases):
+        ref = oracle.OracleLattice(L, q, K, L + q)
+        want = [oracle.cluster_sums(ref.sweep()["labels"]) for _ in range(3)]
+        assert [tuple(x) for x in b.cluster_sums(r, 0, 3).tolist()] == want, r
+    b.close()
+
+
+def test_improved_estimators_on_tiny_lattices_match_exact_moments():
+    cases = [(4, 2), (3, 3)]
+    reps = []
+    for L, q in cases:
+        reps += [dict(L=L, q=q, K=wl.critical_coupling(q), seed=1900 + 37 * q + i, cluster_sums=True)
+                 for i in range(32)]
+    say(f"improved estimators on {len(reps)} tiny replicas")
+    b = binding.Batch(reps, obs_capacity=1001)
+    b.sweep_all(100)
+    rows = [[] for _ in reps]
+    cs = [[] for _ in reps]
+    for c in range(3):
+        b.sweep_all(1000)
+        for r in range(len(reps)):
+            rows[r].append(b.measure(r, 100 + 1000 * c, 1000))
+            cs[r].append(b.cluster_sums(r, 100 + 1000 * c, 1000))
+    b.close()
+    for k, (L, q) in enumerate(cases):
+        sl = range(32 * k, 32 * (k + 1))
+        plain = moments.moments(np.concatenate([np.concatenate(rows[r]) for r in sl]), q, n_blocks=32)
+        imp = moments.improved_moments(np.concatenate([np.concatenate(cs[r]) for r in sl]), L * L, q, n_blocks=32)
+        m2, m4 = exact_moments(L, q, wl.critical_coupling(q))
+        say(f"L={L} q={q}: improved m2 {imp['m2']:.5f} +- {imp['m2_err']:.5f} (plain +- {plain['m2_err']:.5f}, "
+            f"exact {m2:.5f}); m4 {imp['m4']:.5f} +- {imp['m4_err']:.5f} (exact {m4:.5f})")
+        assert abs(imp["m2"] - m2) < 5 * imp["m2_err"]
+        assert abs(imp["m4"] - m4) < 5 * imp["m4_err"]
+        assert imp["m2_err"] < plain["m2_err"]

@@ -86,6 +86,24 @@ def test_many_states(q):
 
 
 @pytest.mark.parametrize("ty", [32, 64, 128])
+@pytest.mark.parametrize("q", [11, 16, 17, 255])
+def test_fused_measurement_many_states(q, ty):
+    """Multi-sweep calls measure each sweep's configuration inside the next
+    sweep's labelling kernel (two-word per-lane counters for q = 9..16, the LDS
+    histogram above); partial tiles (L = 130) and every tile height."""
+    L, K = 130, wl.critical_coupling(q)
+    say(f"fused measurement q={q} ty={ty}")
+    ref = oracle.OracleLattice(L, q, K, 40 + q)
+    rows = ref.run(9)
+    lat = binding.Lattice(L, q, K, seed=40 + q, obs_capacity=16, tile_rows=ty)
+    lat.sweep(4)
+    lat.sweep(5)
+    assert np.array_equal(lat.spins(), ref.s)
+    assert np.array_equal(lat.measure(0, 9), rows)
+    lat.close()
+
+
+@pytest.mark.parametrize("ty", [32, 64, 128])
 @pytest.mark.parametrize("L", [100, 256, 383])
 def test_tile_heights(ty, L):
     compare_sweeps(L, 3, wl.critical_coupling(3), seed=5, sweeps=6, tile_rows=ty)

@@ -90,3 +90,63 @@ def test_crossing_finder():
     assert moments.crossing(K, 1.5 - (K - 1), 1.5 - 2 * (K - 1)) == pytest.approx(1.0, abs=1e-12)
     assert moments.crossing(K, 1.5 - (K - 1.02), 1.5 - 3 * (K - 1.02)) == pytest.approx(1.02, abs=1e-12)
     assert moments.crossing(K, np.ones(11), np.ones(11) * 2) is None
+
+
+# ------------------------------------------- cluster-size improved estimators
+
+@pytest.mark.parametrize("q,density,seed", [(2, 0.3, 1), (3, 0.3, 7), (4, 0.3, 17), (5, 0.3, 13), (2, 0.6, 2)])
+def test_improved_estimators_equal_the_average_over_cluster_states(q, density, seed):
+    """For fixed clusters, enumerate every assignment of states to the clusters:
+    the mean of |M|^2 and |M|^4 must equal the improved estimators computed from
+    the cluster sizes (an identity, checked exactly, not statistically)."""
+    L = 4
+    bx, by = wl.random_bonds(L, density, seed)
+    lab = oracle.label(bx, by).reshape(-1)
+    roots = sorted(set(lab.tolist()))
+    if len(roots) > 9:
+        pytest.skip("too many clusters to enumerate")
+    idx = np.array([roots.index(r) for r in lab])
+    e = simplex(q)
+    m2 = m4 = 0.0
+    count = 0
+    for states in itertools.product(range(q), repeat=len(roots)):
+        M = e[np.array(states)[idx]].sum(axis=0)
+        a = float(M @ M)
+        m2 += a
+        m4 += a * a
+        count += 1
+    N = L * L
+    s2, s4 = oracle.cluster_sums(lab)
+    sizes = np.bincount(idx)
+    assert s2 == int((sizes ** 2).sum()) and s4 == int((sizes ** 4).sum())
+    i2, i4 = moments.improved_from_cluster_sums([(s2, s4)], N, q)
+    assert i2[0] == pytest.approx(m2 / count / N ** 2, rel=1e-12)
+    assert i4[0] == pytest.approx(m4 / count / N ** 4, rel=1e-12)
+
+
+def test_cluster_sums_at_extreme_sizes():
+    # one cluster of 2^30 sites: S2 = 2^60, S4 = 2^120 (exact Python integers)
+    lab = np.zeros(4, dtype=np.uint32)
+    assert oracle.cluster_sums(lab) == (16, 256)
+    m2, m4 = moments.improved_from_cluster_sums([(2 ** 60, 2 ** 120)], 2 ** 30, 2)
+    assert m2[0] == 1.0 and m4[0] == 1.0
+    m2, m4 = moments.improved_from_cluster_sums([(2 ** 60, 2 ** 120)], 2 ** 30, 5)
+    assert m2[0] == 1.0 and m4[0] == 1.0
+
+
+@pytest.mark.parametrize("L,q", [(4, 2), (3, 3)])
+def test_improved_estimators_match_exact_enumeration_and_beat_the_plain_ones(L, q):
+    K = wl.critical_coupling(q)
+    m2, m4 = exact_moments(L, q, K)
+    ref = oracle.OracleLattice(L, q, K, seed=43, random_start=True)
+    ref.run(200)
+    rows, cs = [], []
+    for _ in range(20000):
+        out = ref.sweep()
+        rows.append(out["obs"])
+        cs.append(oracle.cluster_sums(out["labels"]))
+    plain = moments.moments(np.array(rows), q)
+    impr = moments.improved_moments(cs, L * L, q)
+    assert abs(impr["m2"] - m2) < 5 * impr["m2_err"], (impr, m2)
+    assert abs(impr["m4"] - m4) < 5 * impr["m4_err"], (impr, m4)
+    assert impr["m2_err"] < plain["m2_err"]
