@@ -174,6 +174,27 @@ def huge_lattices(warmup: int, steps: int) -> dict:
     return out
 
 
+def small_lattice(sweeps: int) -> dict:
+    """The small correctness configuration (L = 64, q = 2, K_c, random start,
+    measurement every sweep) timed on its own: launch-bound at this size, so
+    the sweeps replay captured HIP graphs."""
+    import torch
+    from paper_1208_2080_amd import binding
+    cfg = workloads()["L64"]
+    L = cfg["L"]
+    lat = binding.Lattice(L, cfg["q"], cfg["K"], seed=cfg["seed"], random_start=cfg["random_start"],
+                          obs_capacity=sweeps + 1)
+    lat.sweep(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.sweep(sweeps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat.close()
+    return {"L": L, "q": cfg["q"], "sweeps": sweeps, "flips_per_ns": L * L * sweeps / (wall * 1e9),
+            "us_per_sweep": wall * 1e6 / sweeps}
+
+
 def _oracle_replica(args):
     import oracle
     r, sweeps = args
@@ -287,6 +308,24 @@ def serving(n_jobs: int, capacity_flips_per_ns: float, tile_rows: int, loads=(0.
         _, stats = srv.run(jobs, realtime=True)
         backend.close()
         out.append(dict(stats, load=load, offered_jobs_per_s=rate))
+    # the same jobs one after another, each as a plain lattice, all at once
+    # (no arrivals): the per-job loop the server is measured against
+    import torch
+    from paper_1208_2080_amd import binding
+    raw = wl.serving_jobs(n=n_jobs, rate_per_s=1.0)
+    print(f"# the {n_jobs} jobs one after another", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in raw:
+        lat = binding.Lattice(j["L"], j["q"], j["K"], seed=j["seed"], obs_capacity=j["sweeps"] + 1,
+                              tile_rows=tile_rows)
+        lat.sweep(j["sweeps"])
+        lat.measure(0, j["sweeps"])
+        lat.spins()
+        lat.close()
+    wall = time.perf_counter() - t0
+    flips = sum(j["L"] ** 2 * j["sweeps"] for j in raw)
+    out.append({"plain_per_job_loop": True, "jobs": n_jobs, "wall_s": wall, "flips_per_ns": flips / (wall * 1e9)})
     return out
 
 
@@ -406,6 +445,7 @@ def main():
         torch.cuda.empty_cache()
     if args.huge:
         out["L65536"] = huge_lattices(2, args.huge)
+    out["L64"] = small_lattice(1000)
     if args.serve:
         out["serving"] = serving(args.serve, value, args.tile_rows)
     if args.batched:

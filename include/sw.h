@@ -121,6 +121,19 @@ int sw_cluster_sums(sw_lattice* h, uint32_t first, uint32_t n, uint64_t* host_ou
  * as sw_sweep's. */
 int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms);
 
+/* sw_measure and sw_read_spins on a stream other than the handle's, for a
+ * caller that keeps the handle's stream busy with further sweeps meanwhile
+ * (continuous batching: the results of one step are read while the next runs;
+ * no paper counterpart).  read_stream (a hipStream_t, not NULL) first waits for
+ * after_event (a hipEvent_t recorded on the handle's stream after the sweeps
+ * to be read, or NULL), then sums the ring records / copies the spins and
+ * synchronises read_stream only.  The caller must not let later sweeps pass
+ * the records being read (obs_capacity) or touch the spins being read.
+ * Same arguments and errors as sw_measure / sw_read_spins otherwise. */
+int sw_measure_after(sw_lattice* h, void* read_stream, void* after_event, uint32_t first, uint32_t n,
+                     int64_t* host_out);
+int sw_read_spins_after(sw_lattice* h, void* read_stream, void* after_event, uint8_t* host_out);
+
 /* Number of sweeps done since sw_init (the index of the next sweep). */
 int sw_sweeps_done(const sw_lattice* h, uint32_t* out);
 

@@ -45,6 +45,8 @@ SIGNATURES = [
     ("sw_sweep", ctypes.c_int, [_VP, _U32]),
     ("sw_measure", ctypes.c_int, [_VP, _U32, _U32, _VP]),
     ("sw_cluster_sums", ctypes.c_int, [_VP, _U32, _U32, _VP]),
+    ("sw_measure_after", ctypes.c_int, [_VP, _VP, _VP, _U32, _U32, _VP]),
+    ("sw_read_spins_after", ctypes.c_int, [_VP, _VP, _VP, _VP]),
     ("sw_sweep_profiled", ctypes.c_int, [_VP, _U32, ctypes.POINTER(ctypes.c_double)]),
     ("sw_sweeps_done", ctypes.c_int, [_VP, ctypes.POINTER(_U32)]),
     ("sw_read_spins", ctypes.c_int, [_VP, _VP]),
@@ -138,6 +140,20 @@ def _stream_handle(stream) -> int:
     return int(stream.cuda_stream)
 
 
+_streams = {}
+
+
+def default_stream(device):
+    """The stream lattices and groups use when none is given: one per device,
+    of default priority, shared so that groups can sweep any lattice made
+    without an explicit stream.  (Not the legacy NULL stream, which the
+    library cannot capture in HIP graphs.)"""
+    device = torch.device(device)
+    if device not in _streams:
+        _streams[device] = torch.cuda.Stream(device)
+    return _streams[device]
+
+
 def derived(row: np.ndarray, L: int, q: int) -> dict:
     """Energy per site e, Potts order parameter m and (q = 2) magnetisation M
     from one int64 observable row [n_unsat, n_active, n_0, ..., n_{q-1}]
@@ -164,8 +180,10 @@ class Lattice:
         if nbytes == 0:
             raise SwError(SW_EINVAL, lib().sw_last_error().decode())
         self.device = torch.device("cuda", 0) if device is None else torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else default_stream(self.device)
         self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.ws.record_stream(self.stream)                      # freed only after the stream's work
+        torch.cuda.current_stream(self.device).synchronize()   # workspace allocated before first use
         self._h = ctypes.c_void_p()
         _check(lib().sw_init(ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
                              ctypes.c_void_p(_stream_handle(self.stream)), ctypes.byref(self._h)))
@@ -197,6 +215,23 @@ class Lattice:
     def measure(self, first: int, n: int) -> np.ndarray:
         out = np.zeros((n, 2 + self.q), dtype=np.int64)
         _check(lib().sw_measure(self._h, int(first), int(n), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def measure_after(self, read_stream, event, first: int, n: int) -> np.ndarray:
+        """``measure`` on read_stream once ``event`` (a torch.cuda.Event recorded
+        on this lattice's stream, or None) has passed; this lattice's stream
+        may keep sweeping meanwhile."""
+        out = np.zeros((n, 2 + self.q), dtype=np.int64)
+        ev = ctypes.c_void_p(event.cuda_event) if event is not None else None
+        _check(lib().sw_measure_after(self._h, ctypes.c_void_p(_stream_handle(read_stream)), ev, int(first), int(n),
+                                      out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def spins_after(self, read_stream, event) -> np.ndarray:
+        out = np.empty((self.L, self.L), dtype=np.uint8)
+        ev = ctypes.c_void_p(event.cuda_event) if event is not None else None
+        _check(lib().sw_read_spins_after(self._h, ctypes.c_void_p(_stream_handle(read_stream)), ev,
+                                         out.ctypes.data_as(ctypes.c_void_p)))
         return out
 
     def cluster_sums(self, first: int, n: int) -> np.ndarray:
@@ -239,8 +274,13 @@ class Lattice:
         out = labels.cpu().numpy().view(np.uint32).reshape(self.L, self.L)
         return out, int(it.value), float(ms.value)
 
-    def close(self):
+    def close(self, sync: bool = True):
+        """Release the lattice.  Its workspace is only reused after the work
+        queued on its stream, so sync=False may skip waiting for that stream
+        (the lattice must not be in any sweep enqueued later)."""
         if self._h:
+            if sync:
+                self.stream.synchronize()
             lib().sw_destroy(self._h)
             self._h = ctypes.c_void_p()
         self.ws = None
@@ -307,6 +347,7 @@ class Batch:
         self.params = arr
         nbytes = ctypes.c_size_t(_batch_bytes(arr))
         self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.ws.record_stream(self.stream)                      # freed only after the stream's work
         torch.cuda.current_stream(self.device).synchronize()   # workspace allocated before first use
         self._h = ctypes.c_void_p()
         _check(lib().sw_batch_init(arr, n, ctypes.c_void_p(self.ws.data_ptr()), nbytes.value,
@@ -347,6 +388,7 @@ class Batch:
 
     def close(self):
         if self._h:
+            self.stream.synchronize()
             lib().sw_batch_destroy(self._h)
             self._h = ctypes.c_void_p()
         self.ws = None
@@ -373,8 +415,10 @@ class Group:
         nbytes = ctypes.c_size_t()
         _check(lib().sw_group_workspace_bytes(self.max_lattices, self.max_tiles, ctypes.byref(nbytes)))
         self.device = torch.device("cuda", 0) if device is None else torch.device(device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else default_stream(self.device)
         self.ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)
+        self.ws.record_stream(self.stream)                      # freed only after the stream's work
+        torch.cuda.current_stream(self.device).synchronize()   # workspace allocated before first use
         self._h = ctypes.c_void_p()
         _check(lib().sw_group_init(self.max_lattices, self.max_tiles, int(tile_rows),
                                    ctypes.c_void_p(self.ws.data_ptr()), nbytes.value,
@@ -389,6 +433,7 @@ class Group:
 
     def close(self):
         if self._h:
+            self.stream.synchronize()
             lib().sw_group_destroy(self._h)
             self._h = ctypes.c_void_p()
         self.ws = None

@@ -173,6 +173,23 @@ LatDesc make_desc(const Geometry& g, const sw_params* p, char* base, const Carve
     return d;
 }
 
+// Captured sweeps: the first sweep of a call (nothing to measure before it),
+// and the next ones one and STEP_CHUNK at a time.  Any number of sweeps
+// replays these three graphs; kernels only, no copies or fills.
+constexpr uint32_t STEP_CHUNK = 16;
+
+struct StepGraphs {
+    hipGraphExec_t first = nullptr, next = nullptr, chunk = nullptr;
+    void clear()
+    {
+        for (hipGraphExec_t* g : {&first, &next, &chunk})
+            if (*g) {
+                (void)hipGraphExecDestroy(*g);
+                *g = nullptr;
+            }
+    }
+};
+
 }  // namespace
 
 // One lattice: host-side view of its slice of the workspace.
@@ -188,6 +205,7 @@ struct sw_lattice {
     uint32_t first_obs;      // first sweep whose observables exist
     bool have_sweep;         // labels and bonds of a sweep are in place
     bool labels_resolved;    // the labels hold smallest site indices (after sw_read_labels)
+    StepGraphs graphs;       // captured sweeps (streams other than the legacy NULL stream)
 };
 
 namespace {
@@ -255,6 +273,56 @@ int enqueue_sweeps(const Work& w, uint32_t n, bool measure, const LatDesc* descs
     if (measure) HIP_TRY(launch_measure(w, n - 1));
     HIP_TRY(launch_bump(descs, count, n_each, n, w.stream));
     if (ev) HIP_TRY(hipEventRecord(ev[3 * n + 1], w.stream));
+    return SW_OK;
+}
+
+// One sweep of every lattice in w with its sweep counter bumped at the end,
+// so that a captured step replays as the next sweep each time.  flags as for
+// launch_bond_label (bit 0: measure the configuration the bonds are drawn on).
+int enqueue_step(const Work& w, uint32_t flags, const LatDesc* descs, uint32_t count)
+{
+    HIP_TRY(launch_bond_label(w, 0, flags));
+    HIP_TRY(launch_merge(w));
+    HIP_TRY(launch_flip(w, 0));
+    if (w.cluster) HIP_TRY(launch_cluster_sums(w, 0));
+    HIP_TRY(launch_bump(descs, count, nullptr, 1, w.stream));
+    return SW_OK;
+}
+
+int capture_steps(const Work& w, uint32_t flags, uint32_t steps, const LatDesc* descs, uint32_t count,
+                  hipGraphExec_t* out)
+{
+    hipGraph_t graph;
+    HIP_TRY(hipStreamBeginCapture(w.stream, hipStreamCaptureModeThreadLocal));
+    int rc = SW_OK;
+    for (uint32_t k = 0; k < steps && rc == SW_OK; ++k) rc = enqueue_step(w, flags, descs, count);
+    const hipError_t ec = hipStreamEndCapture(w.stream, &graph);
+    if (rc != SW_OK) return rc;
+    if (ec != hipSuccess) return fail(SW_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return fail(SW_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    return SW_OK;
+}
+
+// n sweeps from the captured steps (built on first use), then the
+// measurement of the last sweep (the one before the bumped counter).
+int run_steps(StepGraphs& G, const Work& w, uint32_t n, bool measure, const LatDesc* descs, uint32_t count)
+{
+    if (!G.first) {
+        int rc = capture_steps(w, 0u, 1, descs, count, &G.first);
+        if (rc == SW_OK) rc = capture_steps(w, measure ? 1u : 0u, 1, descs, count, &G.next);
+        if (rc == SW_OK) rc = capture_steps(w, measure ? 1u : 0u, STEP_CHUNK, descs, count, &G.chunk);
+        if (rc) {
+            G.clear();
+            return rc;
+        }
+    }
+    HIP_TRY(hipGraphLaunch(G.first, w.stream));
+    uint32_t left = n - 1;
+    for (; left >= STEP_CHUNK; left -= STEP_CHUNK) HIP_TRY(hipGraphLaunch(G.chunk, w.stream));
+    for (; left; --left) HIP_TRY(hipGraphLaunch(G.next, w.stream));
+    if (measure) HIP_TRY(launch_measure(w, 0xFFFFFFFFu));   // counter - 1: the last sweep
     return SW_OK;
 }
 
@@ -328,7 +396,9 @@ int sw_sweep(sw_lattice* h, uint32_t n_sweeps)
     if (n_sweeps == 0) return SW_OK;
     if ((uint64_t)h->done + n_sweeps > 0xFFFFFFFFull) return fail(SW_ESTATE, "sweep counter would overflow");
     const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream, h->g.csum};
-    const int rc = enqueue_sweeps(w, n_sweeps, h->g.cap != 0, h->d_desc, 1, nullptr);
+    // the legacy NULL stream cannot be captured: launch directly
+    const int rc = h->stream ? run_steps(h->graphs, w, n_sweeps, h->g.cap != 0, h->d_desc, 1)
+                             : enqueue_sweeps(w, n_sweeps, h->g.cap != 0, h->d_desc, 1, nullptr);
     if (rc) return rc;
     h->done += n_sweeps;
     h->have_sweep = true;
@@ -386,6 +456,32 @@ int sw_sweeps_done(const sw_lattice* h, uint32_t* out)
     if (!h || !out) return fail(SW_EINVAL, "NULL argument");
     *out = h->done;
     return SW_OK;
+}
+
+int sw_measure_after(sw_lattice* h, void* read_stream, void* after_event, uint32_t first, uint32_t n,
+                     int64_t* host_out)
+{
+    if (!h || !read_stream || (!host_out && n)) return fail(SW_EINVAL, "NULL argument");
+    if (h->g.cap == 0) return fail(SW_ESTATE, "lattice was created with obs_capacity = 0");
+    const uint64_t end = (uint64_t)first + n;
+    const uint64_t lo = std::max<uint64_t>(h->first_obs, h->done > h->g.cap ? h->done - h->g.cap : 0);
+    if (first < lo || end > h->done)
+        return fail(SW_ESTATE, "sweeps [%u, %llu) not available (have [%llu, %u))", first,
+                    (unsigned long long)end, (unsigned long long)lo, h->done);
+    const hipStream_t rs = static_cast<hipStream_t>(read_stream);
+    if (after_event) HIP_TRY(hipStreamWaitEvent(rs, static_cast<hipEvent_t>(after_event), 0));
+    int rc = check_device_error(h->desc, rs);
+    if (rc) return rc;
+    return read_ring(h->desc, h->g.N, rs, first, n, host_out);
+}
+
+int sw_read_spins_after(sw_lattice* h, void* read_stream, void* after_event, uint8_t* host_out)
+{
+    if (!h || !read_stream || !host_out) return fail(SW_EINVAL, "NULL argument");
+    const hipStream_t rs = static_cast<hipStream_t>(read_stream);
+    if (after_event) HIP_TRY(hipStreamWaitEvent(rs, static_cast<hipEvent_t>(after_event), 0));
+    HIP_TRY(hipMemcpyAsync(host_out, h->desc.s, h->g.N, hipMemcpyDeviceToHost, rs));
+    return check_device_error(h->desc, rs);
 }
 
 int sw_measure(sw_lattice* h, uint32_t first, uint32_t n, int64_t* host_out)
@@ -511,6 +607,8 @@ int sw_label_equivalence(sw_lattice* h, uint32_t* dev_labels, uint32_t* dev_flag
 
 int sw_destroy(sw_lattice* h)
 {
+    if (!h) return SW_OK;
+    h->graphs.clear();
     delete h;
     return SW_OK;
 }
@@ -560,12 +658,9 @@ struct sw_batch {
     std::vector<WorkItem> h_map;    // host copy of the last uploaded map
     std::vector<uint32_t> h_n;
     std::vector<uint32_t> map_order;  // replica order of the uploaded map
-    std::map<uint32_t, hipGraphExec_t> graphs;   // sweep_all graphs by sweep count
+    StepGraphs steps;                            // captured sweeps of every replica (sweep_all)
     bool csum = false;                           // some replica measures cluster-size sums
 };
-
-// sweep_all graphs kept per batch (one per distinct sweep count)
-constexpr size_t MAX_GRAPHS = 8;
 
 namespace {
 
@@ -780,8 +875,7 @@ int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps)
         for (uint32_t r = 0; r < b->n; ++r) b->done[r] += n_sweeps;
         return SW_OK;
     }
-    auto it = b->graphs.find(n_sweeps);
-    // the graph bakes in the work map of "every replica"; make sure it is the one uploaded
+    // the captured steps bake in the work map of "every replica"; make sure it is the one uploaded
     std::vector<uint32_t> order(b->n);
     for (uint32_t r = 0; r < b->n; ++r) order[r] = r;
     if (b->map_order != order || b->h_map.empty()) {
@@ -789,41 +883,10 @@ int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps)
         int rc = upload_map(b, all.data(), 1, &prefix);
         if (rc) return rc;
     }
-    if (it == b->graphs.end()) {
-        // a bounded cache: past MAX_GRAPHS sweep counts, drop the older graphs
-        // (after the stream has finished any launch of them)
-        if (b->graphs.size() >= MAX_GRAPHS) {
-            HIP_TRY(hipStreamSynchronize(b->stream));
-            for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-            b->graphs.clear();
-        }
-        const uint32_t M = (uint32_t)b->total_tiles;
-        hipGraph_t graph;
-        HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-        int rc = SW_OK;
-        for (uint32_t k = 0; k < n_sweeps && rc == SW_OK; ++k) {
-            const Work w{b->d_descs, b->d_map, M, b->ty, b->stream, b->csum};
-            if (launch_bond_label(w, k, k > 0 ? 1u : 0u) != hipSuccess || launch_merge(w) != hipSuccess ||
-                launch_flip(w, k) != hipSuccess || (w.cluster && launch_cluster_sums(w, k) != hipSuccess))
-                rc = SW_EHIP;
-        }
-        if (rc == SW_OK) {
-            // the sweep count is a constant of the graph: the measurement of the
-            // last sweep and the counter bump read nothing the host may change
-            const Work w{b->d_descs, b->d_map, M, b->ty, b->stream};
-            if (launch_measure(w, n_sweeps - 1) != hipSuccess ||
-                launch_bump(b->d_descs, b->n, nullptr, n_sweeps, b->stream) != hipSuccess)
-                rc = SW_EHIP;
-        }
-        const hipError_t ec = hipStreamEndCapture(b->stream, &graph);
-        if (rc != SW_OK || ec != hipSuccess) return fail(SW_EHIP, "graph capture failed: %s", hipGetErrorString(ec));
-        hipGraphExec_t exec;
-        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (ei != hipSuccess) return fail(SW_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
-        it = b->graphs.emplace(n_sweeps, exec).first;
-    }
-    HIP_TRY(hipGraphLaunch(it->second, b->stream));
+    const Work w{b->d_descs, b->d_map, (uint32_t)b->total_tiles, b->ty, b->stream, b->csum};
+    // replicas without a ring skip the measurements inside the kernels
+    const int rc = run_steps(b->steps, w, n_sweeps, true, b->d_descs, b->n);
+    if (rc) return rc;
     for (uint32_t r = 0; r < b->n; ++r) b->done[r] += n_sweeps;
     return SW_OK;
 }
@@ -881,7 +944,7 @@ int sw_batch_sweeps_done(const sw_batch* b, uint32_t replica, uint32_t* out)
 int sw_batch_destroy(sw_batch* b)
 {
     if (!b) return SW_OK;
-    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->steps.clear();
     delete b;
     return SW_OK;
 }

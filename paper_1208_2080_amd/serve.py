@@ -12,6 +12,11 @@ never overtaken), so no job starves.
 Every job's random numbers are keyed only by its own seed and its own sweep
 index, so its spins and observables are identical alone and in any mix.
 
+Steps are pipelined: the next step is enqueued before the results of the
+current one are read back, so the host's bookkeeping (copying observables and
+final spins of finished jobs out on a second stream, admitting new jobs)
+overlaps the device's work instead of leaving it idle between steps.
+
 The device work goes through a backend object (``GpuBackend`` here); the
 scheduler itself holds no arithmetic of the method.
 """
@@ -55,20 +60,26 @@ class _Resident:
     tiles: int
     admitted: float
     last: float
-    done: int = 0
+    done: int = 0              # sweeps completed (their step has finished)
+    enq: int = 0               # sweeps enqueued
     unread: int = 0            # sweeps done whose observables are still only on the device
     rows: list = dataclasses.field(default_factory=list)
     lat: list = dataclasses.field(default_factory=list)
 
 
 class GpuBackend:
-    """Jobs as ``binding.Lattice`` objects, stepped together through a ``binding.Group``."""
+    """Jobs as ``binding.Lattice`` objects, stepped together through a
+    ``binding.Group`` on one stream; results are read on a second stream (same
+    priority) after an event that marks the end of their step."""
 
     def __init__(self, max_jobs: int, max_tiles: int, tile_rows: int = 0):
+        import torch
         from . import binding
+        self.torch = torch
         self.binding = binding
         self.tile_rows = tile_rows
         self.group = binding.Group(max_jobs, max_tiles, tile_rows)
+        self.read_stream = torch.cuda.Stream(self.group.device)
 
     def footprint(self, job: Job, obs_capacity: int) -> int:
         return self.binding.workspace_bytes(job.L, job.q, obs_capacity, self.tile_rows)
@@ -83,17 +94,25 @@ class GpuBackend:
     def step(self, handles, n_each):
         self.group.sweep(handles, n_each)
 
-    def sync(self):
-        self.group.stream.synchronize()
+    def mark(self):
+        """A token for the work enqueued so far (an event on the group's stream)."""
+        ev = self.torch.cuda.Event()
+        ev.record(self.group.stream)
+        return ev
 
-    def measure(self, handle, first: int, n: int) -> np.ndarray:
-        return handle.measure(first, n)
+    def wait(self, token):
+        token.synchronize()
 
-    def spins(self, handle) -> np.ndarray:
-        return handle.spins()
+    def measure(self, handle, first: int, n: int, after=None) -> np.ndarray:
+        return handle.measure_after(self.read_stream, after, first, n)
+
+    def spins(self, handle, after=None) -> np.ndarray:
+        return handle.spins_after(self.read_stream, after)
 
     def release(self, handle):
-        handle.close()
+        # its workspace is reused only after the group stream's work; a finished
+        # job is in no later step
+        handle.close(sync=False)
 
     def close(self):
         self.group.close()
@@ -112,9 +131,10 @@ class SwServer:
         self.max_tiles = int(max_tiles)
         self.step_sweeps = int(step_sweeps)
         # observables are copied out every `measure_every` steps (and when a job
-        # ends): the ring keeps that many steps of sweeps
+        # ends): the ring keeps that many steps of sweeps, plus the step that
+        # runs while they are read
         self.measure_every = int(measure_every)
-        self.obs_capacity = self.step_sweeps * self.measure_every + 1
+        self.obs_capacity = self.step_sweeps * (self.measure_every + 1) + 1
         self.clock = clock
         self.peak_bytes = 0
         self.steps = 0
@@ -140,6 +160,35 @@ class SwServer:
         t0 = self.clock()
         now = lambda: self.clock() - t0  # noqa: E731
 
+        inflight = None   # (members, n_each, token) of the step on the device
+
+        def finish(step):
+            """Bookkeeping of a completed step (the next one may be running)."""
+            nonlocal used_bytes, used_tiles
+            members, n_each, token = step
+            self.backend.wait(token)
+            te = now()
+            self.steps += 1
+            for r, n in zip(members, n_each):
+                r.done += n
+                r.unread += n
+                r.lat.append((te - r.last) / n)
+                r.last = te
+                # copy the observables out before the ring could overwrite them
+                # (the step in flight adds up to step_sweeps more)
+                if r.done == r.job.sweeps or r.unread + 2 * self.step_sweeps > self.obs_capacity - 1:
+                    r.rows.append(self.backend.measure(r.handle, r.done - r.unread, r.unread, after=token))
+                    r.unread = 0
+            for r in members:
+                if r.done == r.job.sweeps:
+                    results[r.job.id] = JobResult(r.job.id, np.concatenate(r.rows, axis=0),
+                                                  self.backend.spins(r.handle, after=token), r.job.arrival,
+                                                  r.admitted, te, r.lat)
+                    self.backend.release(r.handle)
+                    used_bytes -= r.bytes
+                    used_tiles -= r.tiles
+                    del resident[r.job.id]
+
         while pending or waiting or resident:
             t = now()
             while pending and (pending[0].arrival <= t or not realtime):
@@ -158,37 +207,23 @@ class SwServer:
                 used_bytes += nb
                 used_tiles += nt
                 self.peak_bytes = max(self.peak_bytes, used_bytes)
-            if not resident:
-                if pending and realtime:
-                    time.sleep(max(0.0, min(pending[0].arrival - now(), 0.01)))
-                continue
-
-            # one step: every resident job advances by up to step_sweeps sweeps
-            members = list(resident.values())
-            n_each = [min(self.step_sweeps, r.job.sweeps - r.done) for r in members]
-            self.backend.step([r.handle for r in members], n_each)
-            self.backend.sync()
-            te = now()
-            self.steps += 1
-            for r, n in zip(members, n_each):
-                r.done += n
-                r.unread += n
-                r.lat.append((te - r.last) / n)
-                r.last = te
-                # copy the observables out before the ring could overwrite them
-                if r.done == r.job.sweeps or r.unread + self.step_sweeps > self.obs_capacity - 1:
-                    r.rows.append(self.backend.measure(r.handle, r.done - r.unread, r.unread))
-                    r.unread = 0
-            # retire finished jobs
-            for r in members:
-                if r.done == r.job.sweeps:
-                    results[r.job.id] = JobResult(r.job.id, np.concatenate(r.rows, axis=0),
-                                                  self.backend.spins(r.handle), r.job.arrival, r.admitted, te,
-                                                  r.lat)
-                    self.backend.release(r.handle)
-                    used_bytes -= r.bytes
-                    used_tiles -= r.tiles
-                    del resident[r.job.id]
+            # the next step: every resident job with sweeps left to enqueue
+            # advances by up to step_sweeps sweeps
+            members = [r for r in resident.values() if r.enq < r.job.sweeps]
+            step = None
+            if members:
+                n_each = [min(self.step_sweeps, r.job.sweeps - r.enq) for r in members]
+                self.backend.step([r.handle for r in members], n_each)
+                for r, n in zip(members, n_each):
+                    r.enq += n
+                step = (members, n_each, self.backend.mark())
+            if inflight is not None:
+                finish(inflight)
+            inflight = step
+            if inflight is None and not resident and pending and realtime:
+                time.sleep(max(0.0, min(pending[0].arrival - now(), 0.01)))
+        if inflight is not None:
+            finish(inflight)
 
         wall = now()
         lats = np.concatenate([np.asarray(res.sweep_latencies) for res in results.values()]) \
