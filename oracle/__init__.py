@@ -1,4 +1,5 @@
-"""CPU oracle for the Swendsen-Wang sweep of the 2D q-state Potts model.
+"""CPU oracle for the Swendsen-Wang sweep of the 2D q-state Potts model and of
+the classical XY model with Wolff's embedded clusters.
 
 TEST INFRASTRUCTURE ONLY.  Only the test suite, ``__graft_entry__.smoke()`` and
 the ``cpu_baseline`` leg of ``bench.py`` may import this package.  The library
@@ -9,7 +10,9 @@ The arithmetic lives in ``sw_oracle.c`` (plain C, one thread); this module only
 compiles it with gcc and marshals arguments.  It follows the paper's three SW
 steps (Sec. 2): bond activation, Hoshen-Kopelman cluster labelling with the
 smallest label as the proper label, and a random new state per cluster, with
-the energy of Eq. (1) counted as the number of unsatisfied bonds.
+the energy of Eq. (1) counted as the number of unsatisfied bonds.  The XY
+sweep (``xy_oracle.c``, the extension of Sec. 5) reuses the same labelling and
+random-number generator with its own streams.
 """
 from __future__ import annotations
 
@@ -20,17 +23,24 @@ import subprocess
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "sw_oracle.c")
+_SRCS = [os.path.join(_HERE, f) for f in ("sw_oracle.c", "xy_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _lib = None
 
 
+def _stale() -> bool:
+    if not os.path.exists(_LIB):
+        return True
+    t = os.path.getmtime(_LIB)
+    return any(os.path.getmtime(f) > t for f in _SRCS + [f[:-2] + ".h" for f in _SRCS])
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc into ``oracle/liboracle.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or _stale():
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -38,7 +48,7 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _stale():
             build(force=True)
         L = ctypes.CDLL(_LIB)
         u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -75,6 +85,26 @@ def lib():
         L.or_run.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_uint64,
                              ctypes.c_uint32, ctypes.c_uint32, u8p, i64p]
         L.or_run.restype = ctypes.c_int
+        u64, u32, dbl = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double
+        for name, res, args in [
+            ("or_xy_direction", u32, [u64, u32, u32]),
+            ("or_xy_initangle", u32, [u64, u64]),
+            ("or_xy_uniform", dbl, [u64, u32, u64, u32]),
+            ("or_xy_flipbit", u32, [u64, u32, u64]),
+            ("or_xy_radians", dbl, [u32]),
+            ("or_xy_projection", dbl, [u32, u32]),
+            ("or_xy_reflect", u32, [u32, u32]),
+            ("or_xy_init", ctypes.c_int, [u32, u64, ctypes.c_int, u32p]),
+            ("or_xy_observe", None, [u32, u32p, i64p]),
+            ("or_xy_derived", None, [u32, dbl, u32p, ctypes.POINTER(dbl)]),
+            ("or_xy_bonds", ctypes.c_int, [u32, dbl, u64, u32, u32, u32p, u8p, u8p]),
+            ("or_xy_flip", ctypes.c_int, [u32, u64, u32, u32, u32p, u8p, u8p, u32p, i64p]),
+            ("or_xy_sweep", ctypes.c_int, [u32, dbl, u64, u32, u32, u32p, u8p, u8p, u32p, i64p]),
+            ("or_xy_run", ctypes.c_int, [u32, dbl, u64, u32, u32, u32, u32p, i64p]),
+        ]:
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
         _lib = L
     return _lib
 
@@ -244,3 +274,131 @@ def pack_bonds(b: np.ndarray) -> np.ndarray:
     padded[:, :L] = b
     bits = np.packbits(padded.reshape(L, W, 64), axis=-1, bitorder="little")  # [L, W, 8]
     return bits.reshape(L, W * 8).view(np.uint64).reshape(L, W)
+
+
+# ------------------------------------------------------------------ XY model
+# The Swendsen-Wang sweep of the classical XY model with Wolff's embedded
+# clusters (the extension of Sec. 5); the arithmetic is in ``xy_oracle.c``,
+# whose header states every convention.  Angles are uint32 turn fractions.
+
+XY_OBS_WORDS = 7
+XY_UNIT = 2.0 ** -30          # one unit of the fixed-point observable sums
+
+
+def xy_direction(seed: int, sweep: int, dir_bits: int = 32) -> int:
+    return int(lib().or_xy_direction(seed, sweep, dir_bits))
+
+
+def xy_initangle(seed: int, site: int) -> int:
+    return int(lib().or_xy_initangle(seed, site))
+
+
+def xy_uniform(seed: int, sweep: int, site: int, direction: int) -> float:
+    return float(lib().or_xy_uniform(seed, sweep, site, direction))
+
+
+def xy_flipbit(seed: int, sweep: int, root: int) -> int:
+    return int(lib().or_xy_flipbit(seed, sweep, root))
+
+
+def xy_radians(a: int) -> float:
+    return float(lib().or_xy_radians(a & 0xFFFFFFFF))
+
+
+def xy_projection(a: int, phi: int) -> float:
+    return float(lib().or_xy_projection(a & 0xFFFFFFFF, phi & 0xFFFFFFFF))
+
+
+def xy_reflect(a: int, phi: int) -> int:
+    return int(lib().or_xy_reflect(a & 0xFFFFFFFF, phi & 0xFFFFFFFF))
+
+
+def xy_init_angles(L: int, seed: int, random_start: bool) -> np.ndarray:
+    a = np.zeros(L * L, dtype=np.uint32)
+    if lib().or_xy_init(L, seed, 1 if random_start else 0, _p(a, ctypes.c_uint32)) != 0:
+        raise ValueError("oracle init rejected its parameters")
+    return a.reshape(L, L)
+
+
+def xy_observe(a: np.ndarray) -> np.ndarray:
+    """[0, Ex, Ey, Ix, Iy, Mx, My] of a configuration in units of 2^-30."""
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    obs = np.zeros(XY_OBS_WORDS, dtype=np.int64)
+    lib().or_xy_observe(a.shape[0], _p(a.reshape(-1), ctypes.c_uint32), _p(obs, ctypes.c_int64))
+    return obs
+
+
+def xy_derived(a: np.ndarray, K: float) -> dict:
+    """Energy per site e, squared magnetisation per site m2 and the helicity
+    estimator Y of one configuration, in FP64 straight from the angles."""
+    a = np.ascontiguousarray(a, dtype=np.uint32)
+    out = np.zeros(3, dtype=np.float64)
+    lib().or_xy_derived(a.shape[0], float(K), _p(a.reshape(-1), ctypes.c_uint32), _p(out, ctypes.c_double))
+    return {"e": float(out[0]), "m2": float(out[1]), "Y": float(out[2])}
+
+
+class XYOracleLattice:
+    """One L x L XY lattice stepped by the oracle.
+
+    ``sweep()`` returns the sweep's direction ``phi``, bonds, labels and the
+    observable row [n_active, Ex, Ey, Ix, Iy, Mx, My] of the configuration
+    after the reflections; ``self.a`` holds the angles (uint32 [L, L]).
+    """
+
+    def __init__(self, L: int, K: float, seed: int, random_start: bool = True, dir_bits: int = 32,
+                 angles: np.ndarray | None = None, sweep: int = 0):
+        self.L, self.K, self.seed, self.dir_bits = int(L), float(K), int(seed), int(dir_bits)
+        if angles is None:
+            self.a = xy_init_angles(self.L, self.seed, random_start)
+        else:
+            self.a = np.ascontiguousarray(angles, dtype=np.uint32).reshape(self.L, self.L).copy()
+        self.t = int(sweep)
+        n = self.L * self.L
+        self.bx = np.zeros(n, dtype=np.uint8)
+        self.by = np.zeros(n, dtype=np.uint8)
+        self.lab = np.zeros(n, dtype=np.uint32)
+
+    def sweep(self) -> dict:
+        obs = np.zeros(XY_OBS_WORDS, dtype=np.int64)
+        phi = xy_direction(self.seed, self.t, self.dir_bits)
+        rc = lib().or_xy_sweep(self.L, self.K, self.seed, self.t, self.dir_bits, _p(self.a.reshape(-1), ctypes.c_uint32),
+                               _p(self.bx, ctypes.c_uint8), _p(self.by, ctypes.c_uint8),
+                               _p(self.lab, ctypes.c_uint32), _p(obs, ctypes.c_int64))
+        if rc != 0:
+            raise ValueError("oracle sweep rejected its parameters")
+        self.t += 1
+        L = self.L
+        return {"phi": phi, "bx": self.bx.reshape(L, L).copy(), "by": self.by.reshape(L, L).copy(),
+                "labels": self.lab.reshape(L, L).copy(), "obs": obs}
+
+    def sweep_steps(self, progress=None) -> np.ndarray:
+        """One sweep as separate calls for its bonds, labels and reflections
+        (progress(name) after each, for long runs); returns the observables."""
+        obs = np.zeros(XY_OBS_WORDS, dtype=np.int64)
+        flat = self.a.reshape(-1)
+        if lib().or_xy_bonds(self.L, self.K, self.seed, self.t, self.dir_bits, _p(flat, ctypes.c_uint32),
+                             _p(self.bx, ctypes.c_uint8), _p(self.by, ctypes.c_uint8)) != 0:
+            raise ValueError("oracle bonds rejected its parameters")
+        if progress:
+            progress("bonds")
+        lib().or_label(self.L, _p(self.bx, ctypes.c_uint8), _p(self.by, ctypes.c_uint8), _p(self.lab, ctypes.c_uint32))
+        if progress:
+            progress("labels")
+        if lib().or_xy_flip(self.L, self.seed, self.t, self.dir_bits, _p(flat, ctypes.c_uint32),
+                            _p(self.bx, ctypes.c_uint8), _p(self.by, ctypes.c_uint8), _p(self.lab, ctypes.c_uint32),
+                            _p(obs, ctypes.c_int64)) != 0:
+            raise ValueError("oracle flip rejected its parameters")
+        if progress:
+            progress("flip")
+        self.t += 1
+        return obs
+
+    def run(self, n: int) -> np.ndarray:
+        """n sweeps; returns the int64 observable rows [n, 7]."""
+        obs = np.zeros((n, XY_OBS_WORDS), dtype=np.int64)
+        rc = lib().or_xy_run(self.L, self.K, self.seed, self.t, n, self.dir_bits,
+                             _p(self.a.reshape(-1), ctypes.c_uint32), _p(obs.reshape(-1), ctypes.c_int64))
+        if rc != 0:
+            raise ValueError("oracle run failed")
+        self.t += n
+        return obs

@@ -10,8 +10,6 @@
 """
 import math
 import os
-import shutil
-import subprocess
 
 import mpmath
 import numpy as np
@@ -28,24 +26,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 # ------------------------------------------------------------------ Philox
-
-@pytest.fixture(scope="session")
-def rocrand_philox(tmp_path_factory):
-    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
-    if not os.path.exists(hipcc):
-        pytest.skip("hipcc not available to build the rocRAND host reference")
-    exe = str(tmp_path_factory.mktemp("rocrand") / "philox_ref")
-    subprocess.check_call([hipcc, "-x", "hip", "--cuda-host-only", "-O1", "-o", exe,
-                           os.path.join(HERE, "rocrand_ref", "philox_ref.cpp")])
-
-    def run(rows):
-        text = "\n".join(" ".join(str(int(v)) for v in r) for r in rows) + "\n"
-        out = subprocess.run([exe], input=text, capture_output=True, text=True, check=True).stdout
-        return np.array([[int(v) for v in line.split()] for line in out.strip().splitlines()],
-                        dtype=np.uint64)
-
-    return run
-
 
 def test_philox_matches_rocrand(rocrand_philox):
     rng = np.random.Generator(np.random.PCG64(7))
