@@ -91,7 +91,7 @@ def lib():
             ("or_xy_initangle", u32, [u64, u64]),
             ("or_xy_uniform", dbl, [u64, u32, u64, u32]),
             ("or_xy_flipbit", u32, [u64, u32, u64]),
-            ("or_xy_radians", dbl, [u32]),
+            ("or_xy_sincos", None, [u32, ctypes.POINTER(dbl), ctypes.POINTER(dbl)]),
             ("or_xy_projection", dbl, [u32, u32]),
             ("or_xy_reflect", u32, [u32, u32]),
             ("or_xy_init", ctypes.c_int, [u32, u64, ctypes.c_int, u32p]),
@@ -301,8 +301,11 @@ def xy_flipbit(seed: int, sweep: int, root: int) -> int:
     return int(lib().or_xy_flipbit(seed, sweep, root))
 
 
-def xy_radians(a: int) -> float:
-    return float(lib().or_xy_radians(a & 0xFFFFFFFF))
+def xy_sincos(a: int):
+    """(sin, cos) of the angle of a, by the oracle's exact quarter-turn reduction."""
+    s, c = ctypes.c_double(), ctypes.c_double()
+    lib().or_xy_sincos(a & 0xFFFFFFFF, ctypes.byref(s), ctypes.byref(c))
+    return float(s.value), float(c.value)
 
 
 def xy_projection(a: int, phi: int) -> float:

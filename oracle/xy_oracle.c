@@ -24,9 +24,14 @@
  * Readings (the paper names the extension only; these are fixed once here and
  * implemented independently by the GPU path from the same written rules):
  *   - an angle is a uint32 a, theta = 2 pi a / 2^32; differences of angles are
- *     exact integers mod 2^32, taken as int32 (a turn in [-1/2, 1/2)) and
- *     converted to radians by one FP64 multiplication by pi / 2^31; the
- *     reflection is exact: a' = 2 a_phi + 2^31 - a (mod 2^32);
+ *     exact integers mod 2^32; the reflection is exact: a' = 2 a_phi + 2^31 - a
+ *     (mod 2^32);
+ *   - sin and cos of an angle a: its nearest quarter turn k is taken off in
+ *     integer arithmetic, the rest d = a - k 2^30 (an int32 in [-2^29, 2^29),
+ *     at most an eighth of a turn) becomes radians by one FP64 multiplication
+ *     by pi / 2^31, and sin, cos of that (C library) are rotated by k quarter
+ *     turns; so a spin exactly a quarter turn from the direction projects to
+ *     zero, and no bond reaches it;
  *   - dir_bits in 1..32: a_phi keeps its top dir_bits bits (the others zero),
  *     so phi is a multiple of 2 pi / 2^dir_bits; 32 is the continuous model;
  *     a cold start with dir_bits = 2 stays on {0, pi} (the Ising model at
@@ -98,15 +103,26 @@ uint32_t or_xy_flipbit(uint64_t seed, uint32_t sweep, uint64_t root)
     return w[0] >> 31;
 }
 
-/* The angle of a turn fraction a (as int32: [-pi, pi)) in radians. */
-double or_xy_radians(uint32_t a)
+/* sin and cos of the angle of a (see the readings above). */
+void or_xy_sincos(uint32_t a, double* s, double* c)
 {
-    return (double)(int32_t)a * ldexp(XY_PI, -31);
+    uint32_t k = ((a + 0x20000000u) >> 30) & 3u;   /* nearest quarter turn */
+    int32_t d = (int32_t)(a - (k << 30));            /* in [-2^29, 2^29) */
+    double x = (double)d * ldexp(XY_PI, -31);
+    double sx = sin(x), cx = cos(x);
+    switch (k) {
+    case 0: *s = sx; *c = cx; break;
+    case 1: *s = cx; *c = -sx; break;
+    case 2: *s = -sx; *c = -cx; break;
+    default: *s = -cx; *c = sx; break;
+    }
 }
 
 double or_xy_projection(uint32_t a, uint32_t phi)
 {
-    return cos(or_xy_radians(a - phi));
+    double s, c;
+    or_xy_sincos(a - phi, &s, &c);
+    return c;
 }
 
 uint32_t or_xy_reflect(uint32_t a, uint32_t phi)
@@ -135,15 +151,16 @@ void or_xy_observe(uint32_t L, const uint32_t* a, int64_t* obs)
         for (uint32_t x = 0; x < L; ++x) {
             uint32_t xr = (x + 1 == L) ? 0 : x + 1;
             uint32_t ai = a[(uint64_t)y * L + x];
-            double dx = or_xy_radians(ai - a[(uint64_t)y * L + xr]);
-            double dy = or_xy_radians(ai - a[(uint64_t)yd * L + x]);
-            double t = or_xy_radians(ai);
-            ex += fx(cos(dx));
-            ey += fx(cos(dy));
-            ix += fx(sin(dx));
-            iy += fx(sin(dy));
-            mx += fx(cos(t));
-            my += fx(sin(t));
+            double sx, cx, sy, cy, st, ct;
+            or_xy_sincos(ai - a[(uint64_t)y * L + xr], &sx, &cx);
+            or_xy_sincos(ai - a[(uint64_t)yd * L + x], &sy, &cy);
+            or_xy_sincos(ai, &st, &ct);
+            ex += fx(cx);
+            ey += fx(cy);
+            ix += fx(sx);
+            iy += fx(sy);
+            mx += fx(ct);
+            my += fx(st);
         }
     }
     obs[0] = 0;
@@ -170,14 +187,16 @@ void or_xy_derived(uint32_t L, double K, const uint32_t* a, double* out)
         for (uint32_t x = 0; x < L; ++x) {
             uint32_t xr = (x + 1 == L) ? 0 : x + 1;
             uint32_t ai = a[(uint64_t)y * L + x];
-            double dx = or_xy_radians(ai - a[(uint64_t)y * L + xr]);
-            double dy = or_xy_radians(ai - a[(uint64_t)yd * L + x]);
-            ex += cos(dx);
-            ey += cos(dy);
-            ix += sin(dx);
-            iy += sin(dy);
-            mx += cos(or_xy_radians(ai));
-            my += sin(or_xy_radians(ai));
+            double sx, cx, sy, cy, st, ct;
+            or_xy_sincos(ai - a[(uint64_t)y * L + xr], &sx, &cx);
+            or_xy_sincos(ai - a[(uint64_t)yd * L + x], &sy, &cy);
+            or_xy_sincos(ai, &st, &ct);
+            ex += cx;
+            ey += cy;
+            ix += sx;
+            iy += sy;
+            mx += ct;
+            my += st;
         }
     }
     out[0] = -(ex + ey) / N;

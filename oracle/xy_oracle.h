@@ -24,7 +24,7 @@ uint32_t or_xy_direction(uint64_t seed, uint32_t sweep, uint32_t dir_bits);
 uint32_t or_xy_initangle(uint64_t seed, uint64_t site);
 double or_xy_uniform(uint64_t seed, uint32_t sweep, uint64_t site, uint32_t dir);
 uint32_t or_xy_flipbit(uint64_t seed, uint32_t sweep, uint64_t root);
-double or_xy_radians(uint32_t a);
+void or_xy_sincos(uint32_t a, double* s, double* c);
 double or_xy_projection(uint32_t a, uint32_t phi);
 uint32_t or_xy_reflect(uint32_t a, uint32_t phi);
 int or_xy_init(uint32_t L, uint64_t seed, int random_start, uint32_t* a);

@@ -17,6 +17,7 @@ form) against things other than itself (no GPU needed).
 """
 import math
 
+import mpmath
 import numpy as np
 import pytest
 from scipy.sparse import coo_matrix
@@ -99,6 +100,38 @@ def test_xy_reflection():
     # the projection the oracle uses is the cosine of the angle to phi
     c = np.array([oracle.xy_projection(int(x), int(p)) for x, p in zip(a, phi)])
     assert np.allclose(c, np.cos(t - f), atol=1e-12)
+
+
+def test_xy_sincos_quarter_turns_exact_and_accurate():
+    for k, want in enumerate([(0.0, 1.0), (1.0, 0.0), (0.0, -1.0), (-1.0, 0.0)]):
+        assert oracle.xy_sincos(k << 30) == want
+    rng = np.random.Generator(np.random.PCG64(9))
+    special = [1, 2**29 - 1, 2**29, 2**29 + 1, 2**30 - 1, 2**30 + 1, 0xDFFFFFFF, 0xE0000000, 0xFFFFFFFF]
+    for a in special + rng.integers(0, 2**32, 3000).tolist():
+        s, c = oracle.xy_sincos(int(a))
+        with mpmath.workdps(40):
+            t = 2 * mpmath.pi * mpmath.mpf(int(a)) / 2**32
+            S, C = mpmath.sin(t), mpmath.cos(t)
+        # each within one unit in the last place of 1 (|sin|, |cos| <= 1)
+        assert abs(s - float(S)) <= 2**-52 and abs(c - float(C)) <= 2**-52, a
+
+
+def test_xy_perpendicular_spins_never_bond():
+    """A spin exactly a quarter turn from the direction has zero projection:
+    even at K = inf it joins no cluster (and its reflection is itself)."""
+    L = 8
+    a = np.zeros((L, L), np.uint32)
+    a[:, ::2] = 2**30
+    lat = oracle.XYOracleLattice(L, float("inf"), 21, dir_bits=2, angles=a)
+    for _ in range(8):
+        before = lat.a.copy()
+        out = lat.sweep()
+        c = np.array([oracle.xy_projection(int(v), out["phi"]) for v in before.reshape(-1)]).reshape(L, L)
+        for key, axis in (("bx", 1), ("by", 0)):
+            cj = np.roll(c, -1, axis=axis)
+            assert not (out[key].astype(bool) & ((c == 0) | (cj == 0))).any()
+            assert np.array_equal(out[key].astype(bool), c * cj > 0)      # K = inf: every other pair
+        assert np.array_equal(lat.a[c == 0], before[c == 0])
 
 
 # ------------------------------------------------------------- whole sweeps
