@@ -34,8 +34,8 @@
  *     zero, and no bond reaches it;
  *   - dir_bits in 1..32: a_phi keeps its top dir_bits bits (the others zero),
  *     so phi is a multiple of 2 pi / 2^dir_bits; 32 is the continuous model;
- *     a cold start with dir_bits = 2 stays on {0, pi} (the Ising model at
- *     coupling K), dir_bits = b on the 2^(b-1)-state clock model;
+ *     a cold start with dir_bits = 1 or 2 stays on {0, pi} (the Ising model at
+ *     coupling K), dir_bits = b >= 2 on the 2^(b-1)-state clock model;
  *   - bond test in FP64: u < -expm1(-((2K) c_i) c_j), evaluated by the site
  *     that owns the bond (i = (x, y), j = (x+1, y) or (x, y+1)), with c_i c_j > 0
  *     required first; K = +inf makes every such bond active;

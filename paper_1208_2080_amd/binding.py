@@ -1,4 +1,5 @@
-"""Python binding of the C ABI in ``include/sw.h`` (argument marshalling only).
+"""Python binding of the C ABI in ``include/sw.h`` and ``include/sw_xy.h``
+(argument marshalling only).
 
 Every step of a sweep runs in the HIP kernels of ``libswmi.so``; this module
 only allocates the device workspace as a torch tensor, hands torch's HIP stream
@@ -34,9 +35,21 @@ class SwParams(ctypes.Structure):
 SW_CLUSTER_SUMS = 1
 
 
-# (name, restype, argtypes) of every function declared in include/sw.h
+class SwXYParams(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_uint32), ("dir_bits", ctypes.c_uint32), ("K", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("init", ctypes.c_uint32), ("obs_capacity", ctypes.c_uint32),
+                ("tile_rows", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+SW_XY_OBS_WORDS = 7
+XY_UNIT = 2.0 ** -30
+
+
+# (name, restype, argtypes) of every function declared in include/sw.h and
+# include/sw_xy.h
 _VP = ctypes.c_void_p
 _PP = ctypes.POINTER(SwParams)
+_XP = ctypes.POINTER(SwXYParams)
 _U32 = ctypes.c_uint32
 SIGNATURES = [
     ("sw_workspace_bytes", ctypes.c_size_t, [_PP]),
@@ -75,6 +88,11 @@ SIGNATURES = [
     ("sw_derived", ctypes.c_int, [_U32, _U32, _VP, _VP]),
     ("sw_sweep_static", ctypes.c_int, [_PP, _VP, _U32, _U32, _VP, _VP, _VP]),
     ("sw_last_error", ctypes.c_char_p, []),
+    ("sw_xy_workspace_bytes", ctypes.c_size_t, [_XP]),
+    ("sw_xy_init", ctypes.c_int, [_XP, _VP, ctypes.c_size_t, _VP, ctypes.POINTER(_VP)]),
+    ("sw_xy_read_angles", ctypes.c_int, [_VP, _VP]),
+    ("sw_xy_load_angles", ctypes.c_int, [_VP, _VP, _U32]),
+    ("sw_xy_derived", ctypes.c_int, [_U32, ctypes.c_double, _VP, _VP]),
 ]
 
 _lib = None
@@ -290,6 +308,77 @@ class Lattice:
             self.close()
         except Exception:
             pass
+
+
+def make_xy_params(L: int, K: float, seed: int = 1, random_start: bool = True, obs_capacity: int = 1024,
+                   tile_rows: int = 0, dir_bits: int = 32) -> SwXYParams:
+    return SwXYParams(int(L), int(dir_bits), float(K), int(seed) & (2**64 - 1), 1 if random_start else 0,
+                      int(obs_capacity), int(tile_rows), 0)
+
+
+def xy_workspace_bytes(L: int, obs_capacity: int = 2, tile_rows: int = 0) -> int:
+    p = make_xy_params(L, 1.0, 1, True, obs_capacity, tile_rows)
+    n = lib().sw_xy_workspace_bytes(ctypes.byref(p))
+    if n == 0:
+        raise SwError(SW_EINVAL, lib().sw_last_error().decode())
+    return int(n)
+
+
+def xy_derived(row: np.ndarray, L: int, K: float) -> dict:
+    """Energy per site e, squared magnetisation per site m2 and the helicity
+    estimator Y from one XY observable row (FP64, by the library's
+    sw_xy_derived)."""
+    r = np.ascontiguousarray(row, dtype=np.int64)
+    assert r.size == SW_XY_OBS_WORDS
+    out = (ctypes.c_double * 3)()
+    _check(lib().sw_xy_derived(int(L), float(K), r.ctypes.data_as(ctypes.c_void_p), out))
+    return {"e": float(out[0]), "m2": float(out[1]), "Y": float(out[2])}
+
+
+class XYLattice(Lattice):
+    """One L x L classical XY lattice (uint32 angles) swept on the GPU with
+    Wolff's embedded clusters; the sweep, labels, bonds, timing and release
+    calls are those of ``Lattice``.  Observable rows are int64
+    [n_active, Ex, Ey, Ix, Iy, Mx, My] (sums in units of 2^-30)."""
+
+    def __init__(self, L: int, K: float, seed: int = 1, random_start: bool = True, obs_capacity: int = 1024,
+                 tile_rows: int = 0, dir_bits: int = 32, device=None, stream=None):
+        self.L, self.q, self.K, self.seed = int(L), 0, float(K), int(seed)
+        self.dir_bits = int(dir_bits)
+        self.obs_capacity = int(obs_capacity)
+        self.params = make_xy_params(L, K, seed, random_start, obs_capacity, tile_rows, dir_bits)
+        nbytes = lib().sw_xy_workspace_bytes(ctypes.byref(self.params))
+        if nbytes == 0:
+            raise SwError(SW_EINVAL, lib().sw_last_error().decode())
+        self.device = torch.device("cuda", 0) if device is None else torch.device(device)
+        self.stream = stream if stream is not None else default_stream(self.device)
+        self.ws = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        self.ws.record_stream(self.stream)
+        torch.cuda.current_stream(self.device).synchronize()
+        self._h = ctypes.c_void_p()
+        _check(lib().sw_xy_init(ctypes.byref(self.params), ctypes.c_void_p(self.ws.data_ptr()), nbytes,
+                                ctypes.c_void_p(_stream_handle(self.stream)), ctypes.byref(self._h)))
+
+    def measure(self, first: int, n: int) -> np.ndarray:
+        out = np.zeros((n, SW_XY_OBS_WORDS), dtype=np.int64)
+        _check(lib().sw_measure(self._h, int(first), int(n), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def measure_after(self, read_stream, event, first: int, n: int) -> np.ndarray:
+        out = np.zeros((n, SW_XY_OBS_WORDS), dtype=np.int64)
+        ev = ctypes.c_void_p(event.cuda_event) if event is not None else None
+        _check(lib().sw_measure_after(self._h, ctypes.c_void_p(_stream_handle(read_stream)), ev, int(first), int(n),
+                                      out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def angles(self) -> np.ndarray:
+        out = np.empty((self.L, self.L), dtype=np.uint32)
+        _check(lib().sw_xy_read_angles(self._h, out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def load_angles(self, a: np.ndarray, sweep: int):
+        a = np.ascontiguousarray(a, dtype=np.uint32).reshape(self.L, self.L)
+        _check(lib().sw_xy_load_angles(self._h, a.ctypes.data_as(ctypes.c_void_p), int(sweep)))
 
 
 def _replica_params(replicas, obs_capacity: int, tile_rows: int):

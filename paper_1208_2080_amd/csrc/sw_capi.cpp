@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/sw.h"
+#include "../../include/sw_xy.h"
 #include "sw_kernels.hpp"
 #include "sw_layout.hpp"
 
@@ -52,13 +53,57 @@ struct Geometry {
     size_t N;
     uint64_t thr;
     bool csum;   // cluster-size sums measured
+    bool xy = false;         // an XY lattice (q unused)
+    uint32_t dir_bits = 0;   // XY: bits of the direction draw kept
+    double K = 0.0;          // XY: the coupling
 };
+
+// Words of a ring record and of one partial copy's stride, for either model.
+inline uint32_t rec_words(const Geometry& g) { return g.xy ? XY_WORDS : ring_words(g.q); }
+inline uint32_t rec_stride(const Geometry& g) { return g.xy ? XY_STRIDE : ring_stride(g.q); }
 
 uint64_t threshold_of(double K)
 {
     if (std::isinf(K)) return 1ull << 32;
     const double p = -std::expm1(-K);    // bond probability 1 - e^{-K}
     return (uint64_t)std::floor(std::ldexp(p, 32));
+}
+
+// The geometry shared by both models: L, tile height, ring capacity.
+int check_common(uint32_t L, uint32_t obs_capacity, uint32_t tile_rows, Geometry* g)
+{
+    if (L < 2 || L > 65536) return fail(SW_EINVAL, "L = %u outside 2..65536", L);
+    if (obs_capacity == 1) return fail(SW_EINVAL, "obs_capacity must be 0 or >= 2");
+    if (obs_capacity > (1u << 28)) return fail(SW_EINVAL, "obs_capacity too large");
+    const uint32_t ty = tile_rows ? tile_rows : DEFAULT_TY;
+    if (ty != 32 && ty != 64 && ty != 128) return fail(SW_EINVAL, "tile_rows must be 0, 32, 64 or 128");
+    g->L = L;
+    g->W = (L + 63) / 64;
+    g->ty = ty;
+    g->ntx = (L + TX - 1) / TX;
+    g->nty = (L + ty - 1) / ty;
+    g->ntiles = g->ntx * g->nty;
+    g->cap = obs_capacity;
+    g->N = (size_t)L * L;
+    return SW_OK;
+}
+
+int check_xy_params(const sw_xy_params* p, Geometry* g)
+{
+    if (!p) return fail(SW_EINVAL, "params is NULL");
+    if (std::isnan(p->K) || p->K < 0) return fail(SW_EINVAL, "K must be >= 0 (got %g)", p->K);
+    if (p->dir_bits < 1 || p->dir_bits > 32) return fail(SW_EINVAL, "dir_bits = %u outside 1..32", p->dir_bits);
+    if (p->init > 1) return fail(SW_EINVAL, "init must be 0 (cold) or 1 (random)");
+    if (p->reserved) return fail(SW_EINVAL, "reserved must be 0");
+    const int rc = check_common(p->L, p->obs_capacity, p->tile_rows, g);
+    if (rc) return rc;
+    g->q = 0;
+    g->thr = 0;
+    g->csum = false;
+    g->xy = true;
+    g->dir_bits = p->dir_bits;
+    g->K = p->K;
+    return SW_OK;
 }
 
 int check_params(const sw_params* p, Geometry* g)
@@ -68,22 +113,12 @@ int check_params(const sw_params* p, Geometry* g)
     if (p->q < 2 || p->q > 255) return fail(SW_EINVAL, "q = %u outside 2..255", p->q);
     if (std::isnan(p->K) || p->K < 0) return fail(SW_EINVAL, "K must be >= 0 (got %g)", p->K);
     if (p->init > 1) return fail(SW_EINVAL, "init must be 0 (cold) or 1 (random)");
-    if (p->obs_capacity == 1) return fail(SW_EINVAL, "obs_capacity must be 0 or >= 2");
-    if (p->obs_capacity > (1u << 28)) return fail(SW_EINVAL, "obs_capacity too large");
-    const uint32_t ty = p->tile_rows ? p->tile_rows : DEFAULT_TY;
-    if (ty != 32 && ty != 64 && ty != 128) return fail(SW_EINVAL, "tile_rows must be 0, 32, 64 or 128");
+    const int rc = check_common(p->L, p->obs_capacity, p->tile_rows, g);
+    if (rc) return rc;
     if (p->flags & ~SW_CLUSTER_SUMS) return fail(SW_EINVAL, "unknown flags 0x%x", p->flags);
     if ((p->flags & SW_CLUSTER_SUMS) && (p->L > 32768 || p->obs_capacity == 0))
         return fail(SW_EINVAL, "cluster sums need L <= 32768 and obs_capacity > 0");
-    g->L = p->L;
     g->q = p->q;
-    g->W = (p->L + 63) / 64;
-    g->ty = ty;
-    g->ntx = (p->L + TX - 1) / TX;
-    g->nty = (p->L + ty - 1) / ty;
-    g->ntiles = g->ntx * g->nty;
-    g->cap = p->obs_capacity;
-    g->N = (size_t)p->L * p->L;
     g->thr = threshold_of(p->K);
     g->csum = (p->flags & SW_CLUSTER_SUMS) != 0;
     return SW_OK;
@@ -109,14 +144,14 @@ Carve carve(const Geometry& g)
     };
     c.state = take(sizeof(DevState));
     c.desc = take(sizeof(LatDesc));
-    c.spins = take(g.N);
+    c.spins = take(g.xy ? g.N * 4 : g.N);
     c.lab = take(g.N * 4);
     c.bonds = take((size_t)g.ntiles * 2 * g.ty * 8);
     c.edges = take((size_t)g.ntiles * edge_words(g.ty) * 4);
     c.nodes = take((size_t)g.ntiles * nslot(g.ty) * 8);
     c.csize = take(g.csum ? (size_t)g.ntiles * nslot(g.ty) * 8 : 0);
-    c.ring = take((size_t)ring_slots(g) * NCOPY * ring_stride(g.q) * 8);
-    c.obs = take((size_t)ring_slots(g) * ring_words(g.q) * 8);
+    c.ring = take((size_t)ring_slots(g) * NCOPY * rec_stride(g) * 8);
+    c.obs = take((size_t)ring_slots(g) * rec_words(g) * 8);
     c.total = off;
     return c;
 }
@@ -141,11 +176,18 @@ bool division_ok(uint32_t L, uint32_t magic, uint32_t shift)
     return true;
 }
 
-LatDesc make_desc(const Geometry& g, const sw_params* p, char* base, const Carve& c)
+LatDesc make_desc(const Geometry& g, uint64_t seed, char* base, const Carve& c)
 {
     LatDesc d{};
     DevState* st = reinterpret_cast<DevState*>(base + c.state);
-    d.s = reinterpret_cast<uint8_t*>(base + c.spins);
+    if (g.xy) {
+        d.ang = reinterpret_cast<uint32_t*>(base + c.spins);
+        d.k2 = 2.0 * g.K;
+        d.dir_keep = g.dir_bits >= 32 ? 0xFFFFFFFFu : ~(0xFFFFFFFFu >> g.dir_bits);
+        d.xy = 1;
+    } else {
+        d.s = reinterpret_cast<uint8_t*>(base + c.spins);
+    }
     d.lab = reinterpret_cast<uint32_t*>(base + c.lab);
     d.bonds = reinterpret_cast<uint64_t*>(base + c.bonds);
     d.edges = reinterpret_cast<uint32_t*>(base + c.edges);
@@ -164,8 +206,8 @@ LatDesc make_desc(const Geometry& g, const sw_params* p, char* base, const Carve
     d.cap = ring_slots(g);
     d.thr_nz = g.thr != 0;
     d.thr_m1 = g.thr ? (uint32_t)(g.thr - 1) : 0u;
-    d.key0 = (uint32_t)p->seed;
-    d.key1 = (uint32_t)(p->seed >> 32);
+    d.key0 = (uint32_t)seed;
+    d.key1 = (uint32_t)(seed >> 32);
     division_magic(g.L, &d.magic, &d.shift);
     d.log2L = 0;
     if ((g.L & (g.L - 1)) == 0)
@@ -194,7 +236,6 @@ struct StepGraphs {
 
 // One lattice: host-side view of its slice of the workspace.
 struct sw_lattice {
-    sw_params p;
     Geometry g;
     Carve c;
     char* base;
@@ -230,11 +271,15 @@ int read_ring(const LatDesc& d, size_t N, hipStream_t s, uint32_t first, uint32_
 {
     if (n == 0) return SW_OK;
     if (n >= d.cap) return fail(SW_ESTATE, "internal: %u records exceed the ring", n);
-    const uint32_t W = ring_words(d.q);
+    const uint32_t W = d.xy ? XY_WORDS : ring_words(d.q);
     std::vector<int64_t> buf((size_t)n * W);
-    HIP_TRY(launch_ring_sum(d.ring, d.obs, d.cap, first % d.cap, n, d.q, s));
+    HIP_TRY(launch_ring_sum(d.ring, d.obs, d.cap, first % d.cap, n, W, d.xy ? XY_STRIDE : ring_stride(d.q), s));
     HIP_TRY(hipMemcpyAsync(buf.data(), d.obs, buf.size() * 8, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    if (d.xy) {   // XY rows are the records themselves
+        std::memcpy(out, buf.data(), buf.size() * 8);
+        return SW_OK;
+    }
     if (cs_out) {
         for (uint32_t k = 0; k < n; ++k)
             for (uint32_t j = 0; j < 3; ++j) cs_out[(size_t)k * 3 + j] = (uint64_t)buf[(size_t)k * W + cs_word(d.q) + j];
@@ -255,6 +300,32 @@ int read_ring(const LatDesc& d, size_t N, hipStream_t s, uint32_t first, uint32_
     return SW_OK;
 }
 
+// The phases of a sweep for either model: the bonds with the labelling
+// (XY: the model's bond kernel, then the labeller over its bond words), the
+// flip (XY: reflections), and the measurement of the last sweep's result.
+int phase_bonds(const Work& w, uint32_t k, uint32_t flags)
+{
+    if (w.xy) {
+        HIP_TRY(launch_xy_bonds(w, k, flags));
+        HIP_TRY(launch_label_preset(w));
+    } else {
+        HIP_TRY(launch_bond_label(w, k, flags));
+    }
+    return SW_OK;
+}
+
+int phase_flip(const Work& w, uint32_t k)
+{
+    HIP_TRY(w.xy ? launch_flip_xy(w, k) : launch_flip(w, k));
+    return SW_OK;
+}
+
+int phase_measure(const Work& w, uint32_t k)
+{
+    HIP_TRY(w.xy ? launch_xy_bonds(w, k, 2u) : launch_measure(w, k));
+    return SW_OK;
+}
+
 // The fixed schedule of n sweeps on one Work description.  With ev (3n + 2
 // events) an event is recorded before the first launch and after every phase.
 int enqueue_sweeps(const Work& w, uint32_t n, bool measure, const LatDesc* descs, uint32_t count,
@@ -262,15 +333,20 @@ int enqueue_sweeps(const Work& w, uint32_t n, bool measure, const LatDesc* descs
 {
     if (ev) HIP_TRY(hipEventRecord(ev[0], w.stream));
     for (uint32_t k = 0; k < n; ++k) {
-        HIP_TRY(launch_bond_label(w, k, (measure && k > 0) ? 1u : 0u));
+        int rc = phase_bonds(w, k, (measure && k > 0) ? 1u : 0u);
+        if (rc) return rc;
         if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 1], w.stream));
         HIP_TRY(launch_merge(w));
         if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 2], w.stream));
-        HIP_TRY(launch_flip(w, k));
+        rc = phase_flip(w, k);
+        if (rc) return rc;
         if (w.cluster) HIP_TRY(launch_cluster_sums(w, k));
         if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 3], w.stream));
     }
-    if (measure) HIP_TRY(launch_measure(w, n - 1));
+    if (measure) {
+        const int rc = phase_measure(w, n - 1);
+        if (rc) return rc;
+    }
     HIP_TRY(launch_bump(descs, count, n_each, n, w.stream));
     if (ev) HIP_TRY(hipEventRecord(ev[3 * n + 1], w.stream));
     return SW_OK;
@@ -281,9 +357,11 @@ int enqueue_sweeps(const Work& w, uint32_t n, bool measure, const LatDesc* descs
 // launch_bond_label (bit 0: measure the configuration the bonds are drawn on).
 int enqueue_step(const Work& w, uint32_t flags, const LatDesc* descs, uint32_t count)
 {
-    HIP_TRY(launch_bond_label(w, 0, flags));
+    int rc = phase_bonds(w, 0, flags);
+    if (rc) return rc;
     HIP_TRY(launch_merge(w));
-    HIP_TRY(launch_flip(w, 0));
+    rc = phase_flip(w, 0);
+    if (rc) return rc;
     if (w.cluster) HIP_TRY(launch_cluster_sums(w, 0));
     HIP_TRY(launch_bump(descs, count, nullptr, 1, w.stream));
     return SW_OK;
@@ -322,7 +400,7 @@ int run_steps(StepGraphs& G, const Work& w, uint32_t n, bool measure, const LatD
     uint32_t left = n - 1;
     for (; left >= STEP_CHUNK; left -= STEP_CHUNK) HIP_TRY(hipGraphLaunch(G.chunk, w.stream));
     for (; left; --left) HIP_TRY(hipGraphLaunch(G.next, w.stream));
-    if (measure) HIP_TRY(launch_measure(w, 0xFFFFFFFFu));   // counter - 1: the last sweep
+    if (measure) return phase_measure(w, 0xFFFFFFFFu);   // counter - 1: the last sweep
     return SW_OK;
 }
 
@@ -347,25 +425,22 @@ int sw_threshold(const sw_params* p, uint64_t* thr)
     return SW_OK;
 }
 
-int sw_init(const sw_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, sw_lattice** out)
+// A lattice of either model in the caller's workspace: descriptor, cleared
+// state and ring, initial spins (angles).
+static int create_lattice(const Geometry& g, uint64_t seed, uint32_t random_start, void* dev_ws, size_t ws_bytes,
+                          void* hip_stream, sw_lattice** out)
 {
-    if (!out) return fail(SW_EINVAL, "out is NULL");
-    *out = nullptr;
-    Geometry g;
-    int rc = check_params(p, &g);
-    if (rc) return rc;
     const Carve c = carve(g);
     if (!dev_ws || ((uintptr_t)dev_ws % ALIGN) != 0)
         return fail(SW_ESPACE, "workspace must be a 256-byte aligned device pointer");
     if (ws_bytes < c.total) return fail(SW_ESPACE, "workspace has %zu bytes, needs %zu", ws_bytes, c.total);
     sw_lattice* h = new (std::nothrow) sw_lattice();
     if (!h) return fail(SW_EINVAL, "out of host memory");
-    h->p = *p;
     h->g = g;
     h->c = c;
     h->base = static_cast<char*>(dev_ws);
     h->stream = static_cast<hipStream_t>(hip_stream);
-    h->desc = make_desc(g, p, h->base, c);
+    h->desc = make_desc(g, seed, h->base, c);
     if (!division_ok(g.L, h->desc.magic, h->desc.shift)) {
         delete h;
         return fail(SW_EINVAL, "internal: division by L self-check failed");
@@ -374,14 +449,15 @@ int sw_init(const sw_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
     auto run = [&]() -> int {
         HIP_TRY(hipMemsetAsync(h->base + c.state, 0, sizeof(DevState), h->stream));
         HIP_TRY(hipMemcpyAsync(h->d_desc, &h->desc, sizeof(LatDesc), hipMemcpyHostToDevice, h->stream));
-        if (g.cap) HIP_TRY(hipMemsetAsync(h->base + c.ring, 0, (size_t)ring_slots(g) * NCOPY * ring_stride(g.q) * 8, h->stream));
+        if (g.cap) HIP_TRY(hipMemsetAsync(h->base + c.ring, 0, (size_t)ring_slots(g) * NCOPY * rec_stride(g) * 8, h->stream));
         if (g.csum) HIP_TRY(hipMemsetAsync(h->base + c.csize, 0, (size_t)g.ntiles * nslot(g.ty) * 8, h->stream));
-        if (p->init) HIP_TRY(launch_init(h->d_desc, 0, g.N, 1u, h->stream));
+        if (g.xy) HIP_TRY(launch_xy_init(h->d_desc, g.N, random_start, h->stream));
+        else if (random_start) HIP_TRY(launch_init(h->d_desc, 0, g.N, 1u, h->stream));
         else HIP_TRY(hipMemsetAsync(h->desc.s, 0, g.N, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
         return SW_OK;
     };
-    rc = run();
+    const int rc = run();
     if (rc) {
         delete h;
         return rc;
@@ -390,12 +466,22 @@ int sw_init(const sw_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
     return SW_OK;
 }
 
+int sw_init(const sw_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, sw_lattice** out)
+{
+    if (!out) return fail(SW_EINVAL, "out is NULL");
+    *out = nullptr;
+    Geometry g;
+    const int rc = check_params(p, &g);
+    if (rc) return rc;
+    return create_lattice(g, p->seed, p->init, dev_ws, ws_bytes, hip_stream, out);
+}
+
 int sw_sweep(sw_lattice* h, uint32_t n_sweeps)
 {
     if (!h) return fail(SW_EINVAL, "handle is NULL");
     if (n_sweeps == 0) return SW_OK;
     if ((uint64_t)h->done + n_sweeps > 0xFFFFFFFFull) return fail(SW_ESTATE, "sweep counter would overflow");
-    const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream, h->g.csum};
+    const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream, h->g.csum, h->g.xy};
     // the legacy NULL stream cannot be captured: launch directly
     const int rc = h->stream ? run_steps(h->graphs, w, n_sweeps, h->g.cap != 0, h->d_desc, 1)
                              : enqueue_sweeps(w, n_sweeps, h->g.cap != 0, h->d_desc, 1, nullptr);
@@ -421,7 +507,7 @@ int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms)
             rc = fail(SW_EHIP, "hipEventCreate failed");
             break;
         }
-    const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream, h->g.csum};
+    const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream, h->g.csum, h->g.xy};
     if (rc == SW_OK) rc = enqueue_sweeps(w, n_sweeps, h->g.cap != 0, h->d_desc, 1, nullptr, ev.data());
     if (rc == SW_OK) {
         h->done += n_sweeps;
@@ -478,6 +564,7 @@ int sw_measure_after(sw_lattice* h, void* read_stream, void* after_event, uint32
 int sw_read_spins_after(sw_lattice* h, void* read_stream, void* after_event, uint8_t* host_out)
 {
     if (!h || !read_stream || !host_out) return fail(SW_EINVAL, "NULL argument");
+    if (h->g.xy) return fail(SW_EINVAL, "an XY lattice holds angles: read them with sw_xy_read_angles");
     const hipStream_t rs = static_cast<hipStream_t>(read_stream);
     if (after_event) HIP_TRY(hipStreamWaitEvent(rs, static_cast<hipEvent_t>(after_event), 0));
     HIP_TRY(hipMemcpyAsync(host_out, h->desc.s, h->g.N, hipMemcpyDeviceToHost, rs));
@@ -515,6 +602,7 @@ int sw_cluster_sums(sw_lattice* h, uint32_t first, uint32_t n, uint64_t* host_ou
 int sw_read_spins(sw_lattice* h, uint8_t* host_out)
 {
     if (!h || !host_out) return fail(SW_EINVAL, "NULL argument");
+    if (h->g.xy) return fail(SW_EINVAL, "an XY lattice holds angles: read them with sw_xy_read_angles");
     HIP_TRY(hipMemcpyAsync(host_out, h->desc.s, h->g.N, hipMemcpyDeviceToHost, h->stream));
     return check_device_error(h->desc, h->stream);
 }
@@ -522,12 +610,13 @@ int sw_read_spins(sw_lattice* h, uint8_t* host_out)
 int sw_load_spins(sw_lattice* h, const uint8_t* host_in, uint32_t sweep)
 {
     if (!h || !host_in) return fail(SW_EINVAL, "NULL argument");
+    if (h->g.xy) return fail(SW_EINVAL, "an XY lattice holds angles: load them with sw_xy_load_angles");
     for (size_t i = 0; i < h->g.N; ++i)
         if (host_in[i] >= h->g.q) return fail(SW_EINVAL, "spin %u at site %zu is not below q", host_in[i], i);
     HIP_TRY(hipMemcpyAsync(h->desc.s, host_in, h->g.N, hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(h->desc.counter, &sweep, sizeof sweep, hipMemcpyHostToDevice, h->stream));
     if (h->g.cap)
-        HIP_TRY(hipMemsetAsync(h->desc.ring, 0, (size_t)ring_slots(h->g) * NCOPY * ring_stride(h->g.q) * 8, h->stream));
+        HIP_TRY(hipMemsetAsync(h->desc.ring, 0, (size_t)ring_slots(h->g) * NCOPY * rec_stride(h->g) * 8, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->done = sweep;
     h->first_obs = sweep;
@@ -630,6 +719,66 @@ int sw_derived(uint32_t L, uint32_t q, const int64_t* row, double* out)
     out[0] = (double)row[0] / Nd;                              // energy per site (units of J)
     out[1] = ((double)q * ((double)most / Nd) - 1.0) / (double)(q - 1);   // Potts order parameter
     out[2] = (q == 2) ? (double)(row[2] - row[3]) : 0.0;         // Ising magnetisation
+    return SW_OK;
+}
+
+// ------------------------------------------------------------------ XY model
+
+size_t sw_xy_workspace_bytes(const sw_xy_params* p)
+{
+    Geometry g;
+    if (check_xy_params(p, &g) != SW_OK) return 0;
+    return carve(g).total;
+}
+
+int sw_xy_init(const sw_xy_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream, sw_lattice** out)
+{
+    if (!out) return fail(SW_EINVAL, "out is NULL");
+    *out = nullptr;
+    Geometry g;
+    const int rc = check_xy_params(p, &g);
+    if (rc) return rc;
+    return create_lattice(g, p->seed, p->init, dev_ws, ws_bytes, hip_stream, out);
+}
+
+int sw_xy_read_angles(sw_lattice* h, uint32_t* host_out)
+{
+    if (!h || !host_out) return fail(SW_EINVAL, "NULL argument");
+    if (!h->g.xy) return fail(SW_EINVAL, "not an XY lattice");
+    HIP_TRY(hipMemcpyAsync(host_out, h->desc.ang, h->g.N * 4, hipMemcpyDeviceToHost, h->stream));
+    return check_device_error(h->desc, h->stream);
+}
+
+int sw_xy_load_angles(sw_lattice* h, const uint32_t* host_in, uint32_t sweep)
+{
+    if (!h || !host_in) return fail(SW_EINVAL, "NULL argument");
+    if (!h->g.xy) return fail(SW_EINVAL, "not an XY lattice");
+    HIP_TRY(hipMemcpyAsync(h->desc.ang, host_in, h->g.N * 4, hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(h->desc.counter, &sweep, sizeof sweep, hipMemcpyHostToDevice, h->stream));
+    if (h->g.cap)
+        HIP_TRY(hipMemsetAsync(h->desc.ring, 0, (size_t)ring_slots(h->g) * NCOPY * rec_stride(h->g) * 8, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->done = sweep;
+    h->first_obs = sweep;
+    h->have_sweep = false;
+    h->labels_resolved = false;
+    return SW_OK;
+}
+
+int sw_xy_derived(uint32_t L, double K, const int64_t* row, double* out)
+{
+    if (!row || !out) return fail(SW_EINVAL, "NULL argument");
+    if (L < 2 || L > 65536) return fail(SW_EINVAL, "L = %u outside 2..65536", L);
+    if (std::isnan(K) || K < 0) return fail(SW_EINVAL, "K must be >= 0 (got %g)", K);
+    const double N = (double)L * (double)L;
+    const double lim = N * 1073741824.0;   // |a sum| <= N in units of 2^-30
+    for (int j = 1; j < (int)XY_WORDS; ++j)
+        if (std::fabs((double)row[j]) > lim) return fail(SW_EINVAL, "word %d of the row exceeds N", j);
+    const double u = 1.0 / 1073741824.0;   // 2^-30
+    const double ex = row[1] * u, ey = row[2] * u, ix = row[3] * u, iy = row[4] * u, mx = row[5] * u, my = row[6] * u;
+    out[0] = -(ex + ey) / N;                                     // energy per site (units of J)
+    out[1] = (mx * mx + my * my) / (N * N);                      // squared magnetisation per site
+    out[2] = (0.5 * (ex + ey) - K * 0.5 * (ix * ix + iy * iy)) / N;   // helicity estimator (units of J)
     return SW_OK;
 }
 
@@ -816,7 +965,7 @@ int sw_batch_init(const sw_params* params, uint32_t n, void* dev_ws, size_t ws_b
     b->desc.resize(n);
     for (uint32_t r = 0; r < n; ++r) b->csum = b->csum || b->g[r].csum;
     for (uint32_t r = 0; r < n; ++r) {
-        b->desc[r] = make_desc(b->g[r], &params[r], b->base + b->off[r], b->c[r]);
+        b->desc[r] = make_desc(b->g[r], params[r].seed, b->base + b->off[r], b->c[r]);
         if (!division_ok(b->g[r].L, b->desc[r].magic, b->desc[r].shift)) {
             delete b;
             return fail(SW_EINVAL, "internal: division by L self-check failed");
@@ -1104,6 +1253,7 @@ int sw_group_sweep(sw_group* g, sw_lattice* const* lats, const uint32_t* n_sweep
     for (uint32_t i = 0; i < n; ++i) {
         const sw_lattice* h = lats[i];
         if (!h) return fail(SW_EINVAL, "lattice %u is NULL", i);
+        if (h->g.xy) return fail(SW_EINVAL, "lattice %u is an XY lattice; groups step Potts lattices", i);
         if (h->g.ty != g->ty) return fail(SW_EINVAL, "lattice %u has tile_rows %u, group %u", i, h->g.ty, g->ty);
         if (h->stream != g->stream) return fail(SW_EINVAL, "lattice %u is bound to another stream", i);
         if ((uint64_t)h->done + n_sweeps[i] > 0xFFFFFFFFull)
@@ -1265,7 +1415,7 @@ extern "C" int sw_sweep_static(const sw_params* p, uint8_t* dev_spins, uint32_t 
     pc.obs = c.ring;   // no read staging in this form
     Geometry gq = g;
     gq.cap = q.obs_capacity;
-    LatDesc d = make_desc(gq, &q, base, pc);
+    LatDesc d = make_desc(gq, q.seed, base, pc);
     if (!division_ok(g.L, d.magic, d.shift)) return fail(SW_EINVAL, "internal: division by L self-check failed");
     d.s = dev_spins;
     d.obs = nullptr;

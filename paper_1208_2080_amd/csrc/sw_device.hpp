@@ -82,6 +82,23 @@ __device__ __forceinline__ uint32_t cluster_state(const LatDesc& d, uint32_t r, 
     return state_of_draw(philox4x32_10(r, 0u, t, 1u, d.key0, d.key1).x, d.q);
 }
 
+// XY lattices (Wolff's embedded clusters): the direction of sweep t, a uint32
+// angle of which the top dir_bits are kept (Philox stream 3), and the
+// reflection bit of the cluster whose root is r (stream 5, the top bit).
+__device__ __forceinline__ uint32_t xy_direction(const LatDesc& d, uint32_t t)
+{
+    return philox4x32_10(0u, 0u, t, 3u, d.key0, d.key1).x & d.dir_keep;
+}
+
+__device__ __forceinline__ uint32_t xy_flip_bit(const LatDesc& d, uint32_t r, uint32_t t)
+{
+    return philox4x32_10(r, 0u, t, 5u, d.key0, d.key1).x >> 31;
+}
+
+// theta -> 2 phi + pi - theta: the reflection across the line perpendicular to
+// the direction phi, exact in turn units.
+__device__ __forceinline__ uint32_t xy_reflect(uint32_t a, uint32_t phi) { return 2u * phi + 0x80000000u - a; }
+
 // -------------------------------------------------------------- division
 // n / L for any 32-bit n by multiply-high (Granlund & Montgomery, PLDI'94,
 // unsigned division by an invariant with a 33-bit multiplier).

@@ -18,6 +18,7 @@
 
 #include "sw_device.hpp"
 #include "sw_kernels.hpp"
+#include "sw_tile.hpp"
 
 namespace swmi {
 
@@ -31,63 +32,8 @@ constexpr uint32_t LDS_CAP = 1u << 15;     // cap of union retries in LDS (> sit
 constexpr uint32_t UNITE_CAP = 1u << 12;   // cap of union retries in the global forest
 constexpr uint32_t SPW = TX + 4;           // LDS row stride of staged spins (bytes)
 
-// Waves of a tile workgroup: every wave owns 16 rows of a 64- or 128-row tile
-// (8 of a 32-row tile), one column per lane.
-template <int TY>
-constexpr uint32_t waves_of() { return TY == 128 ? 8u : 4u; }
-template <int TY>
-constexpr uint32_t threads_of() { return 64u * waves_of<TY>(); }
-
-struct TileGeom {
-    uint32_t tx, ty, x0, y0, w, h;
-};
-
-__device__ __forceinline__ TileGeom tile_geom(const LatDesc& d, uint32_t tile, uint32_t ty_rows)
-{
-    TileGeom g;
-    g.ty = tile / d.ntx;
-    g.tx = tile - g.ty * d.ntx;
-    g.x0 = g.tx * TX;
-    g.y0 = g.ty * ty_rows;
-    g.w = min(TX, d.L - g.x0);
-    g.h = min(ty_rows, d.L - g.y0);
-    return g;
-}
-
-// Which lattice (lat) and tile this workgroup (or wave) works on.  Without a
-// map the work is the tiles of lattice 0, optionally spread over the XCDs so
-// that each gets a contiguous band of tiles.  Mapped work (many lattices of
-// uneven cost) keeps the hardware's round-robin dealing, which balances the
-// XCDs better than bands do.
-__device__ __forceinline__ bool pick(const LatDesc* descs, const WorkItem* map, uint32_t idx,
-                                     bool spread, LatDesc& d, uint32_t& tile, uint32_t& lat)
-{
-    if (map) {
-        const WorkItem it = map[idx];
-        if (it.lat == INVALID) return false;
-        d = descs[it.lat];
-        tile = it.tile;
-        lat = it.lat;
-        return true;
-    }
-    lat = 0;
-    d = descs[0];
-    if (idx >= d.ntiles) return false;
-    tile = spread ? xcd_tile(idx, d.ntiles) : idx;
-    return true;
-}
-
-__device__ __forceinline__ void flag_error(uint32_t* err)
-{
-    __hip_atomic_fetch_or(glb(err), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Lane l's bit of a wave-uniform mask, as a lane predicate.
 __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
-
-// Index of this wave in its workgroup as a wave-uniform (scalar) value, for
-// kernels where work selected by it (descriptor loads) should stay scalar.
-__device__ __forceinline__ uint32_t wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // Sum over the wave of a per-lane value below 2^BITS, bit plane by bit plane
 // (one ballot per plane: cheaper than 64 atomics on one LDS word).
@@ -401,12 +347,6 @@ __device__ __forceinline__ int64_t* ring_record(const LatDesc& d, uint32_t sweep
     return d.ring + ((size_t)(sweep % d.cap) * NCOPY + copy) * ring_stride(d.q);   // cast at the access
 }
 
-__device__ __forceinline__ void atomic_add_i64(int64_t* p, uint64_t v)
-{
-    __hip_atomic_fetch_add(glb(reinterpret_cast<unsigned long long*>(p)), (unsigned long long)v, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // Per-wave queue of pending unions (pairs of provisional labels, 16 bits
 // each).  Row labelling never reads the union-find, so unions can wait and
 // then run with every lane busy instead of one lane of a diverged wave.
@@ -487,7 +427,9 @@ __device__ __forceinline__ uint32_t row_labels(uint16_t* P, uint32_t* rl, UnionQ
 //
 // flags bit 0: also measure the configuration the bonds are drawn on (the
 // result of the previous sweep, t - 1).
-template <int TY>
+// PRESET: the bonds are already in the bond plane (drawn by the XY model's own
+// kernel); the kernel then only labels, and measures nothing.
+template <int TY, bool PRESET = false>
 __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_eu(8))) void k_bond_label(const LatDesc* descs, const WorkItem* map, uint32_t k,
                                                    uint32_t flags)
 {
@@ -512,14 +454,22 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     if (!pick(descs, map, blockIdx.x, true, d, tile, lat)) return;
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t t = *glb(d.counter) + k;
-    const bool meas = d.cap != 0;
+    const bool meas = !PRESET && d.cap != 0;
     const bool meas_prev = meas && (flags & 1u);
     const uint32_t tid = threadIdx.x, wave = wave_id(), lane = tid & 63u;
     const uint32_t L = d.L, w = g.w, h = g.h, x0 = g.x0, y0 = g.y0;
 
     if (tid < 256) hist[tid] = 0;
     if (tid < 3) tot[tid] = 0;
-    stage_spins<TY>(sp, d, g, tid);
+    if constexpr (PRESET) {
+        const gptr<uint64_t> bin = glb(d.bonds) + (size_t)tile * 2 * TY;
+        for (uint32_t j = tid; j < 2 * TY; j += NT) {
+            const uint32_t r = j % TY;
+            rb[r][j / TY] = r < h ? bin[j] : 0ull;
+        }
+    } else {
+        stage_spins<TY>(sp, d, g, tid);
+    }
     __syncthreads();
 
     const uint32_t x = lane;
@@ -631,7 +581,18 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
             }
         }
     };
-    if (q16 && !q8) strip_rows(std::true_type{});
+    // the same row labelling over bond words that are already in LDS
+    auto preset_rows = [&]() {
+        for (uint32_t r = r0; r < r1; ++r) {
+            if (uq.n > QCAP - 64) drain(uq, P, lane, bad);
+            const uint64_t hx = rb[r][0] & ~cross;
+            lp = row_labels(P, rl, uq, r, x, validm, hx, vprev, hprev, lp);
+            hprev = hx;
+            vprev = rb[r][1];
+        }
+    };
+    if constexpr (PRESET) preset_rows();
+    else if (q16 && !q8) strip_rows(std::true_type{});
     else strip_rows(std::false_type{});
     seam[wave][lane] = lp;
     if (meas_prev) {
@@ -665,7 +626,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     for (uint32_t j0 = 0; j0 < 2 * TY; j0 += NT) {
         const uint32_t j = j0 + tid, r = j % TY;
         const uint64_t word = (j < 2 * TY && r < h) ? rb[r][j / TY] : 0ull;
-        if (j < 2 * TY && r < h) bw[j] = word;
+        if (!PRESET && j < 2 * TY && r < h) bw[j] = word;
         if (meas) {
             const uint32_t n = wave_sum_small<7>(popc64(word));   // active bonds
             if (lane == 0 && n) atomicAdd(&tot[1], n);
@@ -880,7 +841,10 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
 // loaded first.  LDS entries are 16 bits (so more workgroups fit a CU): a
 // tile-local index, ROOT16 | slot for a node, ROOT16 | RES16 | state for a
 // resolved root inside the tile.
-template <int TY>
+// XY: the draw per cluster is a reflection bit instead of a state, and each
+// site of a reflected cluster has its angle reflected across the line
+// perpendicular to the sweep's direction (the others are not touched).
+template <int TY, bool XY = false>
 __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_eu(8))) void k_flip(
     const LatDesc* descs, const WorkItem* map, uint32_t k)
 {
@@ -915,6 +879,8 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     const gptr<const char> lab_tile = (gptr<const char>)(glb(d.lab) + (size_t)y0 * L + x0);
     const gptr<char> s_tile = (gptr<char>)(glb(d.s) + (size_t)y0 * L + x0);
     const uint32_t n_used = min(glb(d.edges)[(size_t)tile * edge_words(TY) + 6], NS);
+    // XY: the sweep's direction (wave-uniform)
+    const uint32_t phi = XY ? __builtin_amdgcn_readfirstlane(xy_direction(d, t)) : 0u;
 
     // Full tiles (the common case) need no masks for columns or rows outside.
     auto body = [&](auto full) {
@@ -969,7 +935,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
             const bool node = (e & NODE_ENTRY) != 0u;
             const uint32_t idx = e & ~NODE_ENTRY;
             const uint32_t key = node ? NK[idx & (NKN - 1u)] : __umul24(y0 + idx / TX, L) + x0 + idx % TX;
-            const uint32_t st = cluster_state(d, key, t);
+            const uint32_t st = XY ? xy_flip_bit(d, key, t) : cluster_state(d, key, t);
             if (act && node) NK[idx & (NKN - 1u)] = st;
             if (act && !node) E[idx & (TY * TX - 1u)] = ROOT16 | RES16 | st;
         }
@@ -978,25 +944,43 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         // Every site follows in-tile pointers (each to a smaller tile index, so
         // the walk ends) to a root: resolved inside the tile, or a node whose
         // state is in the table; the new spins are stored at the end.
-        uint32_t e[PER];
-#pragma unroll
-        for (uint32_t j = 0; j < PER; ++j) {
-            const uint32_t r = wave + NW * j;
-            e[j] = 0;
-            if (vcol && (FULL || r < h)) {
-                uint32_t cur = li0 + j * NW * TX, x = E[cur];
-                while (!(x & ROOT16) && x < cur) {
-                    cur = x;
-                    x = E[cur];
-                }
-                bad |= !(x & ROOT16);
-                e[j] = (x & RES16) ? x : NK[x & (NKN - 1u)];
+        auto walk = [&](uint32_t j) -> uint32_t {
+            uint32_t cur = li0 + j * NW * TX, x = E[cur];
+            while (!(x & ROOT16) && x < cur) {
+                cur = x;
+                x = E[cur];
             }
-        }
+            bad |= !(x & ROOT16);
+            return (x & RES16) ? x : NK[x & (NKN - 1u)];
+        };
+        if constexpr (XY) {
+            // one bit per row (reflect or not) keeps the loop's registers few
+            uint32_t bits = 0;
 #pragma unroll
-        for (uint32_t j = 0; j < PER; ++j) {
-            const uint32_t r = wave + NW * j;
-            if (vcol && (FULL || r < h)) *(gptr<uint8_t>)(s_tile + (site0 + j * wave_step)) = (uint8_t)e[j];
+            for (uint32_t j = 0; j < PER; ++j) {
+                const uint32_t r = wave + NW * j;
+                if (vcol && (FULL || r < h)) bits |= (walk(j) & 1u) << j;
+            }
+            const gptr<char> a_tile = (gptr<char>)(glb(d.ang) + (size_t)y0 * L + x0);
+#pragma unroll 1
+            for (uint32_t j = 0; j < PER; ++j) {
+                if ((bits >> j) & 1u) {
+                    const gptr<uint32_t> p = (gptr<uint32_t>)(a_tile + (site0 + j * wave_step) * 4u);
+                    *p = xy_reflect(*p, phi);
+                }
+            }
+        } else {
+            uint32_t e[PER];
+#pragma unroll
+            for (uint32_t j = 0; j < PER; ++j) {
+                const uint32_t r = wave + NW * j;
+                e[j] = (vcol && (FULL || r < h)) ? walk(j) : 0u;
+            }
+#pragma unroll
+            for (uint32_t j = 0; j < PER; ++j) {
+                const uint32_t r = wave + NW * j;
+                if (vcol && (FULL || r < h)) *(gptr<uint8_t>)(s_tile + (site0 + j * wave_step)) = (uint8_t)e[j];
+            }
         }
     };
     if (w == TX && h == TY) body(std::true_type{});
@@ -1005,7 +989,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
 
     // The ring record of the next sweep starts from zero.
     if (d.cap && tile == 0) {
-        const uint32_t words = NCOPY * ring_stride(d.q);
+        const uint32_t words = NCOPY * (XY ? XY_STRIDE : ring_stride(d.q));
         gptr<int64_t> rec = glb(d.ring) + (size_t)((t + 1) % d.cap) * words;
         for (uint32_t i = tid; i < words; i += NT) rec[i] = 0;
     }
@@ -1254,14 +1238,13 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_resolve(const LatDesc* des
 // One thread per (record, word): the sum of the word over the record's NCOPY
 // partial copies.
 __global__ __launch_bounds__(256) void k_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, uint32_t slot0,
-                                                  uint32_t n, uint32_t q)
+                                                  uint32_t n, uint32_t W, uint32_t stride)
 {
-    const uint32_t W = ring_words(q);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n * W) return;
     const uint32_t rec = i / W, w = i - rec * W;
     const uint32_t slot = (uint32_t)(((uint64_t)slot0 + rec) % slots);
-    const size_t R = ring_stride(q);
+    const size_t R = stride;
     const gptr<const int64_t> base = glb(ring) + (size_t)slot * NCOPY * R + w;
     int64_t sum = 0;
 #pragma unroll 8
@@ -1353,6 +1336,30 @@ hipError_t launch_bond_label(const Work& w, uint32_t k, uint32_t flags)
     return hipGetLastError();
 }
 
+hipError_t launch_label_preset(const Work& w)
+{
+    if (w.nitems == 0) return hipSuccess;
+    switch (w.ty) {
+    case 32: hipLaunchKernelGGL((k_bond_label<32, true>), dim3(w.nitems), dim3(threads_of<32>()), 0, w.stream, w.descs, w.map, 0u, 0u); break;
+    case 64: hipLaunchKernelGGL((k_bond_label<64, true>), dim3(w.nitems), dim3(threads_of<64>()), 0, w.stream, w.descs, w.map, 0u, 0u); break;
+    case 128: hipLaunchKernelGGL((k_bond_label<128, true>), dim3(w.nitems), dim3(threads_of<128>()), 0, w.stream, w.descs, w.map, 0u, 0u); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_xy(const Work& w, uint32_t k)
+{
+    if (w.nitems == 0) return hipSuccess;
+    switch (w.ty) {
+    case 32: hipLaunchKernelGGL((k_flip<32, true>), dim3(w.nitems), dim3(threads_of<32>()), 0, w.stream, w.descs, w.map, k); break;
+    case 64: hipLaunchKernelGGL((k_flip<64, true>), dim3(w.nitems), dim3(threads_of<64>()), 0, w.stream, w.descs, w.map, k); break;
+    case 128: hipLaunchKernelGGL((k_flip<128, true>), dim3(w.nitems), dim3(threads_of<128>()), 0, w.stream, w.descs, w.map, k); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_merge(const Work& w)
 {
     if (w.nitems == 0) return hipSuccess;
@@ -1407,13 +1414,14 @@ hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, uint32_t ntiles, u
     return hipGetLastError();
 }
 
-hipError_t launch_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, uint32_t slot0, uint32_t n, uint32_t q,
-                           hipStream_t s)
+hipError_t launch_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, uint32_t slot0, uint32_t n,
+                           uint32_t words, uint32_t stride, hipStream_t s)
 {
-    const uint64_t total = (uint64_t)n * ring_words(q);
+    const uint64_t total = (uint64_t)n * words;
     if (total == 0) return hipSuccess;
-    if (total > 0xFFFFFFFFull || slot0 >= slots || n >= slots) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_ring_sum, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, ring, out, slots, slot0, n, q);
+    if (total > 0xFFFFFFFFull || slot0 >= slots || n >= slots || words > stride) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_ring_sum, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, ring, out, slots, slot0, n,
+                       words, stride);
     return hipGetLastError();
 }
 

@@ -18,6 +18,7 @@ struct Work {
     uint32_t ty;
     hipStream_t stream;
     bool cluster = false;  // some lattice measures cluster-size sums
+    bool xy = false;       // XY lattices (Wolff's embedded clusters)
 };
 
 hipError_t launch_bond_label(const Work& w, uint32_t k, uint32_t flags);
@@ -30,12 +31,22 @@ hipError_t launch_cluster_sums(const Work& w, uint32_t k);
 // measurement after n_each[lattice] sweeps of each lattice (batched form)
 hipError_t launch_measure_each(const Work& w, const uint32_t* n_each);
 hipError_t launch_init(const LatDesc* descs, uint32_t lat, size_t N, uint32_t random_start, hipStream_t s);
+
+// XY lattices: the bond step of sweep counter + k (flags bit 0: also measure
+// the incoming configuration; bit 1: only measure the current one, k =
+// 0xFFFFFFFF naming the last sweep), the labeller over those bonds, the flip
+// as reflections, and the initial angles.
+hipError_t launch_xy_bonds(const Work& w, uint32_t k, uint32_t flags);
+hipError_t launch_label_preset(const Work& w);
+hipError_t launch_flip_xy(const Work& w, uint32_t k);
+hipError_t launch_xy_init(const LatDesc* descs, size_t N, uint32_t random_start, hipStream_t s);
 // Labels of the last sweep resolved in place to smallest site indices.
 hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, uint32_t ntiles, uint32_t ty, hipStream_t s);
-// Sum the NCOPY partial copies of n ring records, from slot slot0 on (wrapping
-// at `slots`), into out[n][q + 1].
-hipError_t launch_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, uint32_t slot0, uint32_t n, uint32_t q,
-                           hipStream_t s);
+// Sum the NCOPY partial copies of n ring records of `words` words (copies
+// `stride` words apart), from slot slot0 on (wrapping at `slots`), into
+// out[n][words].
+hipError_t launch_ring_sum(const int64_t* ring, int64_t* out, uint32_t slots, uint32_t slot0, uint32_t n,
+                           uint32_t words, uint32_t stride, hipStream_t s);
 hipError_t launch_bump(const LatDesc* descs, uint32_t count, const uint32_t* n_each, uint32_t n, hipStream_t s);
 
 // No-allocation entry point: copy the descriptor d to d_out, clear the error

@@ -3,7 +3,8 @@
 // Per lattice (site i = y*L + x, row-major; tiles of TX = 64 columns by TY
 // rows, numbered row-major; a site's tile-local index is r*TX + c for row r,
 // column c of its tile):
-//   spins   uint8  [N]
+//   spins   uint8  [N]        Potts states; for an XY lattice uint32 [N]
+//                             angles instead (unit: 2^-32 of a full turn)
 //   labels  uint32 [N]        after a sweep, per site: the tile-local index of a
 //                             smaller site of its tile-local cluster (its
 //                             union-find grandparent in the tile), or, for the
@@ -22,6 +23,7 @@
 //                             forest's roots are the clusters' smallest sites
 //   ring    int64  [slots][NCOPY][ring_stride(q)]  per-sweep sums: n_unsat,
 //                             n_active, n_1..n_{q-1} (n_0 = N - the rest);
+//                             an XY lattice's records are XY_WORDS long
 //                             NCOPY partial copies, each on cache lines of its
 //                             own, spread the workgroups' atomics
 //   obs     int64  [slots][q + 1]  staging for reads: the NCOPY partial copies of
@@ -66,6 +68,13 @@ __host__ __device__ constexpr uint32_t cs_word(uint32_t q) { return q + 1u; }
 // to whole 256-byte blocks, so no two copies share a cache line.
 __host__ __device__ constexpr uint32_t ring_stride(uint32_t q) { return (ring_words(q) + 31u) & ~31u; }
 
+// Ring record of an XY lattice: n_active, then the sums over sites of
+// cos(theta_i - theta_{i+x}), cos(theta_i - theta_{i+y}), sin of the same two
+// differences, cos theta_i and sin theta_i, each term rounded to a multiple of
+// 2^-30 (so the sums are exact integers, whatever the order of addition).
+constexpr uint32_t XY_WORDS = 7;
+constexpr uint32_t XY_STRIDE = (XY_WORDS + 31u) & ~31u;
+
 struct DevState {
     uint32_t err;          // nonzero: a safety cap tripped
     uint32_t counter;      // sweeps done (plain lattice)
@@ -91,6 +100,11 @@ struct LatDesc {
     uint32_t key0, key1;
     uint32_t magic, shift; // division by L
     uint32_t log2L;        // log2 L when L is a power of two, else 0
+    // XY lattices (null / zero for Potts)
+    uint32_t* ang;         // angles, uint32 [N]
+    double k2;             // 2K (may be +inf)
+    uint32_t dir_keep;     // bits of the direction draw kept (the top dir_bits)
+    uint32_t xy;           // 1: an XY lattice
 };
 
 // Block-to-work map entry of the batched form: lattice index and tile index.

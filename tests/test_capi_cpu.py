@@ -1,5 +1,5 @@
 """The C-ABI library builds, loads without a GPU and exports every function that
-include/sw.h declares; host-side logic (parameter checks, workspace sizes, the
+include/*.h declares; host-side logic (parameter checks, workspace sizes, the
 bond threshold) behaves as documented.  No kernel runs here."""
 import ctypes
 import math
@@ -16,7 +16,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared_functions():
-    text = open(os.path.join(ROOT, "include", "sw.h")).read()
+    inc = os.path.join(ROOT, "include")
+    text = "".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(sw_[a-z_]+)\s*\(", text)))
 
@@ -151,3 +152,50 @@ def test_derived_rejects_bad_rows():
                       (row, 1, 2), (row, 65537, 2), (row, 2, 1), (row, 2, 256)]:
         rc = binding.lib().sw_derived(L, q, bad.ctypes.data_as(ctypes.c_void_p), out)
         assert rc == binding.SW_EINVAL, (bad, L, q)
+
+
+# ------------------------------------------------------------------ XY model
+
+def _xy_ws(L, cap=2, ty=0, bits=32, K=1.0):
+    p = binding.make_xy_params(L, K, obs_capacity=cap, tile_rows=ty, dir_bits=bits)
+    return binding.lib().sw_xy_workspace_bytes(ctypes.byref(p))
+
+
+def test_xy_parameter_checks_and_workspace():
+    assert _xy_ws(64) > 0 and _xy_ws(64) % 256 == 0
+    # angles are 4 bytes a site: 3 more than a Potts lattice's states
+    for L in (64, 1000, 4096):
+        assert _xy_ws(L) - _ws(L) >= 3 * L * L - 1024      # (regions are 256-byte aligned)
+    assert 34.0 * 2**30 < _xy_ws(65536, 1024) < 37.0 * 2**30     # ~8.3 B/site + edge records and forest
+    for bad in [dict(L=1), dict(L=65537), dict(bits=0), dict(bits=33), dict(K=-1.0), dict(K=float("nan")),
+                dict(ty=48), dict(cap=1)]:
+        args = dict(L=64, cap=2, ty=0, bits=32, K=1.0)
+        args.update(bad)
+        assert _xy_ws(**args) == 0, bad
+    p = binding.make_xy_params(64, 1.0)
+    p.reserved = 1
+    assert binding.lib().sw_xy_workspace_bytes(ctypes.byref(p)) == 0
+    assert _xy_ws(64, K=float("inf")) > 0
+
+
+def test_xy_derived_matches_oracle_values():
+    """sw_xy_derived from the oracle's fixed-point row against the oracle's own
+    FP64 values from the angles: each of the six sums is off by at most N 2^-31
+    (one rounding to 2^-30 per term)."""
+    import numpy as np
+    rng = np.random.Generator(np.random.PCG64(4))
+    for L, K in [(16, 0.7), (33, 1.3), (64, 0.0)]:
+        a = rng.integers(0, 2**32, (L, L), dtype=np.uint64).astype(np.uint32)
+        row = oracle.xy_observe(a)
+        got = binding.xy_derived(row, L, K)
+        ref = oracle.xy_derived(a, K)
+        N = L * L
+        eps = N * 2.0**-31                       # bound on each sum's rounding
+        assert abs(got["e"] - ref["e"]) <= 2 * eps / N * (1 + 1e-9)
+        mx, my = row[5] * binding.XY_UNIT, row[6] * binding.XY_UNIT
+        assert abs(got["m2"] - ref["m2"]) <= (2 * (abs(mx) + abs(my)) * eps + 2 * eps * eps) / N**2 * (1 + 1e-6)
+        ix, iy = row[3] * binding.XY_UNIT, row[4] * binding.XY_UNIT
+        bound = (eps + K * ((abs(ix) + abs(iy)) * eps + eps * eps)) / N
+        assert abs(got["Y"] - ref["Y"]) <= bound * (1 + 1e-6) + 1e-15
+    with pytest.raises(binding.SwError):
+        binding.xy_derived(np.array([0, 2**62, 0, 0, 0, 0, 0]), 16, 1.0)    # |Ex| > N
