@@ -13,7 +13,6 @@ and the CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -24,6 +23,11 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, vendor figure
+FP64_PEAK_TFLOPS = 78.6          # MI355X dense FP64 vector, vendor figure
+# FP64 arithmetic of the XY bond kernel per site, a neighbour's values counted
+# once: sin and cos of the angle (37), the projection (3), the two bond tests
+# (7: the FP32 estimates not counted), the measurement terms (30)
+XY_BOND_FLOPS_PER_SITE = 77
 # algorithmic bytes per site of one launch (uint8 spins, uint32 labels, 2-bit bonds)
 KERNEL_BYTES_PER_SITE = {
     "k_bond_label": 1.0 + 0.25 + 4.0,   # read spins, write bond planes, write labels
@@ -45,11 +49,8 @@ def workloads():
 
 
 def kernel_source_digest() -> str:
-    h = hashlib.sha256()
-    for name in ("sw_kernels.hip", "sw_device.hpp", "sw_layout.hpp"):
-        with open(os.path.join(ROOT, "paper_1208_2080_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
+    from paper_1208_2080_amd.profiling import kernel_source_digest as digest
+    return digest()
 
 
 def measured_traffic(kernel: str, workload: str, tile_rows: int):
@@ -193,6 +194,53 @@ def small_lattice(sweeps: int) -> dict:
     lat.close()
     return {"L": L, "q": cfg["q"], "sweeps": sweeps, "flips_per_ns": L * L * sweeps / (wall * 1e9),
             "us_per_sweep": wall * 1e6 / sweeps}
+
+
+def xy_lattice(warmup: int, steps: int, with_cpu: bool) -> dict:
+    """The XY model (Wolff's embedded clusters) on the same machinery: an
+    L = 16384 lattice near the KT coupling, random start, measurement every
+    sweep; per-phase device times from HIP events (bonds + labels, merge,
+    reflections, final measurement), and the XY oracle on one L = 4096 sweep."""
+    import torch
+    from paper_1208_2080_amd import binding
+    from paper_1208_2080_amd import workloads as wl
+    cfg = dict(wl.XY_16384)
+    L, K = cfg["L"], cfg["K"]
+    lat = binding.XYLattice(L, K, seed=cfg["seed"], random_start=True, obs_capacity=steps + 1)
+    print(f"# XY L={L} K={K}: {warmup} + {steps} sweeps", file=sys.stderr, flush=True)
+    lat.sweep(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ph = lat.sweep_profiled(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    row = lat.measure(lat.sweeps_done - 1, 1)[0]
+    d = binding.xy_derived(row, L, K)
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    out = {"workload": f"SW sweep with embedded clusters, 2D XY L={L} K={K} periodic, random start, "
+                       f"update + measurement", "L": L, "K": K, "sweeps": steps,
+           "flips_per_ns": L * L * steps / (wall * 1e9), "ms_per_sweep": wall * 1e3 / steps,
+           "phase_ms_per_sweep": {"k_xy_bonds+k_bond_label": ph[0] / steps, "k_merge": ph[1] / steps,
+                                  "k_flip(reflect)": ph[2] / steps, "final measure": ph[3]},
+           "energy_per_site_last": d["e"]}
+    bond_ms = ph[4] / steps
+    achieved = XY_BOND_FLOPS_PER_SITE * L * L / (bond_ms * 1e-3) / 1e12
+    out["roofline"] = {"bound": "alu", "kernel": "k_xy_bonds", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
+                       "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                       "traffic": measured_traffic("k_xy_bonds", "xyL16384", 64),
+                       "alg_flops_per_launch": XY_BOND_FLOPS_PER_SITE * L * L, "avg_launch_ms": bond_ms}
+    if with_cpu:
+        import oracle
+        Lc = cfg["cpu_L"]
+        ref = oracle.XYOracleLattice(Lc, K, cfg["seed"])
+        t0 = time.perf_counter()
+        ref.sweep()
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": Lc * Lc / (dt * 1e9), "unit": "spin flips/ns", "cores": 1, "kind": "oracle",
+                             "sample": f"one XY sweep (with measurement) of L = {Lc}"}
+    return out
 
 
 def _oracle_replica(args):
@@ -344,6 +392,10 @@ def main():
                     help="time 256 uneven replicas batched vs one after another for SWEEPS sweeps (0: skip)")
     ap.add_argument("--huge", type=int, default=10, metavar="SWEEPS",
                     help="time SWEEPS sweeps of the L = 65536 lattices, q = 2 and 3 (0: skip)")
+    ap.add_argument("--small", type=int, default=1000, metavar="SWEEPS",
+                    help="time SWEEPS sweeps of the L = 64 lattice (0: skip)")
+    ap.add_argument("--xy", type=int, default=50, metavar="SWEEPS",
+                    help="time SWEEPS sweeps of the L = 16384 XY lattice (0: skip)")
     ap.add_argument("--serve", type=int, default=0, metavar="JOBS",
                     help="also run the server on JOBS Poisson jobs at 0.5, 0.9 and 1.2 x capacity")
     ap.add_argument("--label-equivalence", type=int, default=0, metavar="SWEEPS",
@@ -445,7 +497,10 @@ def main():
         torch.cuda.empty_cache()
     if args.huge:
         out["L65536"] = huge_lattices(2, args.huge)
-    out["L64"] = small_lattice(1000)
+    if args.small:
+        out["L64"] = small_lattice(args.small)
+    if args.xy:
+        out["xy_L16384"] = xy_lattice(5, args.xy, not args.no_cpu_baseline)
     if args.serve:
         out["serving"] = serving(args.serve, value, args.tile_rows)
     if args.batched:

@@ -115,10 +115,12 @@ int sw_cluster_sums(sw_lattice* h, uint32_t first, uint32_t n, uint64_t* host_ou
 
 /* sw_sweep with timing: HIP events are recorded on the handle's stream around
  * every kernel launch; the call then synchronises and writes the summed device
- * time of each phase, in milliseconds, into phase_ms[4]: [0] bonds + tile
+ * time of each phase, in milliseconds, into phase_ms[5]: [0] bonds + tile
  * labels (+ measurement of the incoming configuration), [1] tile-edge merge,
- * [2] flip, [3] final measurement and counter update.  The results are the same
- * as sw_sweep's. */
+ * [2] flip, [3] final measurement and counter update, [4] the part of [0]
+ * spent in the model's bond kernel (the XY model's k_xy_bonds; for the Potts
+ * model, whose bonds and labels are one kernel, equal to [0]).  The results
+ * are the same as sw_sweep's. */
 int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms);
 
 /* sw_measure and sw_read_spins on a stream other than the handle's, for a

@@ -219,8 +219,9 @@ class Lattice:
 
     def sweep_profiled(self, n: int) -> np.ndarray:
         """n sweeps with HIP events around every kernel; returns the summed device
-        milliseconds of [bonds + tile labels, merge, flip, final measurement]."""
-        out = (ctypes.c_double * 4)()
+        milliseconds of [bonds + tile labels, merge, flip, final measurement,
+        the bond kernel alone (part of the first)]."""
+        out = (ctypes.c_double * 5)()
         _check(lib().sw_sweep_profiled(self._h, int(n), out))
         return np.array(out[:], dtype=np.float64)
 

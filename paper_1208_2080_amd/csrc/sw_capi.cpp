@@ -303,13 +303,15 @@ int read_ring(const LatDesc& d, size_t N, hipStream_t s, uint32_t first, uint32_
 // The phases of a sweep for either model: the bonds with the labelling
 // (XY: the model's bond kernel, then the labeller over its bond words), the
 // flip (XY: reflections), and the measurement of the last sweep's result.
-int phase_bonds(const Work& w, uint32_t k, uint32_t flags)
+int phase_bonds(const Work& w, uint32_t k, uint32_t flags, hipEvent_t after_bonds = nullptr)
 {
     if (w.xy) {
         HIP_TRY(launch_xy_bonds(w, k, flags));
+        if (after_bonds) HIP_TRY(hipEventRecord(after_bonds, w.stream));
         HIP_TRY(launch_label_preset(w));
     } else {
         HIP_TRY(launch_bond_label(w, k, flags));
+        if (after_bonds) HIP_TRY(hipEventRecord(after_bonds, w.stream));
     }
     return SW_OK;
 }
@@ -326,29 +328,30 @@ int phase_measure(const Work& w, uint32_t k)
     return SW_OK;
 }
 
-// The fixed schedule of n sweeps on one Work description.  With ev (3n + 2
-// events) an event is recorded before the first launch and after every phase.
+// The fixed schedule of n sweeps on one Work description.  With ev (4n + 2
+// events) an event is recorded before the first launch, after the bond kernel
+// and after every phase.
 int enqueue_sweeps(const Work& w, uint32_t n, bool measure, const LatDesc* descs, uint32_t count,
                    const uint32_t* n_each, hipEvent_t* ev = nullptr)
 {
     if (ev) HIP_TRY(hipEventRecord(ev[0], w.stream));
     for (uint32_t k = 0; k < n; ++k) {
-        int rc = phase_bonds(w, k, (measure && k > 0) ? 1u : 0u);
+        int rc = phase_bonds(w, k, (measure && k > 0) ? 1u : 0u, ev ? ev[4 * k + 1] : nullptr);
         if (rc) return rc;
-        if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 1], w.stream));
+        if (ev) HIP_TRY(hipEventRecord(ev[4 * k + 2], w.stream));
         HIP_TRY(launch_merge(w));
-        if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 2], w.stream));
+        if (ev) HIP_TRY(hipEventRecord(ev[4 * k + 3], w.stream));
         rc = phase_flip(w, k);
         if (rc) return rc;
         if (w.cluster) HIP_TRY(launch_cluster_sums(w, k));
-        if (ev) HIP_TRY(hipEventRecord(ev[3 * k + 3], w.stream));
+        if (ev) HIP_TRY(hipEventRecord(ev[4 * k + 4], w.stream));
     }
     if (measure) {
         const int rc = phase_measure(w, n - 1);
         if (rc) return rc;
     }
     HIP_TRY(launch_bump(descs, count, n_each, n, w.stream));
-    if (ev) HIP_TRY(hipEventRecord(ev[3 * n + 1], w.stream));
+    if (ev) HIP_TRY(hipEventRecord(ev[4 * n + 1], w.stream));
     return SW_OK;
 }
 
@@ -495,11 +498,11 @@ int sw_sweep(sw_lattice* h, uint32_t n_sweeps)
 int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms)
 {
     if (!h || !phase_ms) return fail(SW_EINVAL, "NULL argument");
-    for (int i = 0; i < 4; ++i) phase_ms[i] = 0.0;
+    for (int i = 0; i < 5; ++i) phase_ms[i] = 0.0;
     if (n_sweeps == 0) return SW_OK;
     if ((uint64_t)h->done + n_sweeps > 0xFFFFFFFFull) return fail(SW_ESTATE, "sweep counter would overflow");
     if (n_sweeps > (1u << 20)) return fail(SW_EINVAL, "profile at most 2^20 sweeps per call");
-    std::vector<hipEvent_t> ev(3 * (size_t)n_sweeps + 2, nullptr);
+    std::vector<hipEvent_t> ev(4 * (size_t)n_sweeps + 2, nullptr);
     int rc = SW_OK;
     // timing-only events: no system-scope fence (cache write-back) at each one
     for (auto& e : ev)
@@ -515,22 +518,22 @@ int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms)
         h->labels_resolved = false;
         if (hipEventSynchronize(ev.back()) != hipSuccess) rc = fail(SW_EHIP, "hipEventSynchronize failed");
     }
-    for (uint32_t k = 0; rc == SW_OK && k < n_sweeps; ++k) {
-        for (int ph = 0; ph < 3; ++ph) {
-            float ms = 0.f;
-            if (hipEventElapsedTime(&ms, ev[3 * k + ph], ev[3 * k + ph + 1]) != hipSuccess) {
-                rc = fail(SW_EHIP, "hipEventElapsedTime failed");
-                break;
-            }
-            phase_ms[ph] += ms;
-        }
-    }
-    if (rc == SW_OK) {
+    // events of sweep k: 4k start, 4k+1 after the bond kernel, 4k+2 after the
+    // labels, 4k+3 after the merge, 4k+4 after the flip (the next sweep's start)
+    auto elapsed = [&](size_t a, size_t b, double& acc) {
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ev[3 * (size_t)n_sweeps], ev.back()) != hipSuccess)
-            rc = fail(SW_EHIP, "hipEventElapsedTime failed");
-        phase_ms[3] = ms;
+        if (hipEventElapsedTime(&ms, ev[a], ev[b]) != hipSuccess) return fail(SW_EHIP, "hipEventElapsedTime failed");
+        acc += ms;
+        return SW_OK;
+    };
+    for (uint32_t k = 0; rc == SW_OK && k < n_sweeps; ++k) {
+        const size_t b = 4 * (size_t)k;
+        rc = elapsed(b, b + 2, phase_ms[0]);
+        if (rc == SW_OK) rc = elapsed(b + 2, b + 3, phase_ms[1]);
+        if (rc == SW_OK) rc = elapsed(b + 3, b + 4, phase_ms[2]);
+        if (rc == SW_OK) rc = elapsed(b, b + 1, phase_ms[4]);
     }
+    if (rc == SW_OK) rc = elapsed(4 * (size_t)n_sweeps, ev.size() - 1, phase_ms[3]);
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     if (rc == SW_OK) rc = check_device_error(h->desc, h->stream);

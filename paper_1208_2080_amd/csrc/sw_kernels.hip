@@ -961,13 +961,20 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
                 const uint32_t r = wave + NW * j;
                 if (vcol && (FULL || r < h)) bits |= (walk(j) & 1u) << j;
             }
+            // the reflected sites' angles in batches of eight: all loads of a
+            // batch in flight together, then its stores
             const gptr<char> a_tile = (gptr<char>)(glb(d.ang) + (size_t)y0 * L + x0);
+            constexpr uint32_t B = PER < 8 ? PER : 8;
 #pragma unroll 1
-            for (uint32_t j = 0; j < PER; ++j) {
-                if ((bits >> j) & 1u) {
-                    const gptr<uint32_t> p = (gptr<uint32_t>)(a_tile + (site0 + j * wave_step) * 4u);
-                    *p = xy_reflect(*p, phi);
-                }
+            for (uint32_t j0 = 0; j0 < PER; j0 += B) {
+                uint32_t av[B];
+#pragma unroll
+                for (uint32_t j = 0; j < B; ++j)
+                    av[j] = ((bits >> (j0 + j)) & 1u) ? *(gptr<const uint32_t>)(a_tile + (site0 + (j0 + j) * wave_step) * 4u) : 0u;
+#pragma unroll
+                for (uint32_t j = 0; j < B; ++j)
+                    if ((bits >> (j0 + j)) & 1u)
+                        *(gptr<uint32_t>)(a_tile + (site0 + (j0 + j) * wave_step) * 4u) = xy_reflect(av[j], phi);
             }
         } else {
             uint32_t e[PER];

@@ -29,15 +29,15 @@ COPY_BYTES = 1 << 30
 
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    for name in ("sw_kernels.hip", "sw_device.hpp", "sw_layout.hpp"):
+    for name in ("sw_kernels.hip", "sw_xy.hip", "sw_tile.hpp", "sw_device.hpp", "sw_layout.hpp"):
         with open(os.path.join(HERE, "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def _short(name: str) -> str:
-    base = name.split("(")[0].replace("void ", "").replace("swmi::", "")
-    return base
+    base = name.replace("(anonymous namespace)::", "").split("(")[0]
+    return base.replace("void ", "").replace("swmi::", "")
 
 
 def _find(d: str, suffix: str) -> str:
@@ -47,14 +47,32 @@ def _find(d: str, suffix: str) -> str:
     return sorted(hits)[0]
 
 
+def _grid(r) -> int:
+    for key in ("Grid_Size", "Grid_Size_X"):
+        if key in r and r[key] not in ("", None):
+            return int(float(r[key]))
+    return 0
+
+
 def stats(d: str, cmd: str) -> str:
-    rows = list(csv.DictReader(open(_find(d, "kernel_stats.csv"))))
-    out = ["# rocprofv3 kernel-trace summary", f"# command: {cmd}",
-           f"# kernel_source_sha256_16: {kernel_source_digest()}",
-           f"{'kernel':60s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
-    for r in rows:
-        out.append(f"{_short(r['Name'])[:60]:60s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.2f} "
-                   f"{float(r['TotalDurationNs']) / 1e6:10.3f} {float(r['Percentage']):6.2f}")
+    """Per-kernel dispatch counts and average durations from the kernel trace;
+    each kernel counts only its dispatches of the largest grid in the run (the
+    workload the run was made for, not smaller side runs of the same kernel)."""
+    by_name = defaultdict(list)
+    for r in csv.DictReader(open(_find(d, "kernel_trace.csv"))):
+        by_name[_short(r["Kernel_Name"])].append((_grid(r), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    rows = []
+    for name, v in by_name.items():
+        g = max(x[0] for x in v)
+        durs = [x[1] for x in v if x[0] == g]
+        rows.append((name, g, len(durs), sum(durs) / len(durs), sum(durs)))
+    total = sum(r[4] for r in rows)
+    rows.sort(key=lambda r: -r[4])
+    out = ["# rocprofv3 kernel-trace summary (per kernel: its dispatches of the largest grid)",
+           f"# command: {cmd}", f"# kernel_source_sha256_16: {kernel_source_digest()}",
+           f"{'kernel':44s} {'grid':>10s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for name, g, n, avg, tot in rows:
+        out.append(f"{name[:44]:44s} {g:10d} {n:7d} {avg / 1e3:10.2f} {tot / 1e6:10.3f} {100 * tot / total:6.2f}")
     return "\n".join(out) + "\n"
 
 
@@ -62,16 +80,17 @@ def _counter_means(d: str, counter: str):
     """Average value of `counter` per dispatch, by kernel (summed over the
     counter's instances within a dispatch)."""
     per_dispatch = defaultdict(float)
-    names = {}
+    names, grids = {}, {}
     for r in csv.DictReader(open(_find(d, "counter_collection.csv"))):
         if r["Counter_Name"] != counter:
             continue
         key = r["Dispatch_Id"]
         per_dispatch[key] += float(r["Counter_Value"])
         names[key] = r["Kernel_Name"]
+        grids[key] = _grid(r)
     by_kernel = defaultdict(list)
     for key, v in per_dispatch.items():
-        by_kernel[names[key]].append(v)
+        by_kernel[names[key]].append((grids[key], v))
     return by_kernel
 
 
@@ -80,15 +99,16 @@ def pmc(fetch_dir: str, write_dir: str, kernel: str, cmd_fetch: str, cmd_write: 
     write = _counter_means(write_dir, "WRITE_SIZE")
 
     def pick(table):
-        vals = [v for name, vs in table.items() if _short(name).startswith(kernel + "<") or _short(name) == kernel
-                for v in vs]
-        if not vals:
+        # the kernel's instantiation named exactly, its dispatches of the largest grid
+        vs = [gv for name, gvs in table.items() if _short(name) == kernel for gv in gvs]
+        if not vs:
             raise SystemExit(f"kernel {kernel} not in the counters")
-        return vals
+        g = max(x[0] for x in vs)
+        return [x[1] for x in vs if x[0] == g]
 
     def copy_reading(table):
         # the largest blit copy of the run is the 1 GiB calibration copy
-        vals = [v for name, vs in table.items() if "copyBuffer" in name for v in vs]
+        vals = [v for name, gvs in table.items() if "copyBuffer" in name for _, v in gvs]
         if not vals:
             raise SystemExit("no device copy in the counters (run with --copy-calibration)")
         return max(vals)

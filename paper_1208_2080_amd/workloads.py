@@ -29,6 +29,13 @@ HUGE_Q2 = {"L": 65536, "q": 2, "K": critical_coupling(2), "seed": 1, "random_sta
 HUGE_Q3 = {"L": 65536, "q": 3, "K": critical_coupling(3), "seed": 1, "random_start": False, "sweeps": 200}
 
 
+# The XY model with embedded clusters (the extension of Sec. 5): K near the
+# Kosterlitz-Thouless coupling of the square lattice (T_KT / J ~ 0.893),
+# random start; the oracle's CPU timing uses one sweep of the smaller lattice.
+K_KT_XY = 1.0 / 0.893
+XY_16384 = {"L": 16384, "K": K_KT_XY, "seed": 1, "random_start": True, "cpu_L": 4096}
+
+
 def random_spins(L: int, q: int, seed: int) -> np.ndarray:
     """Uniform spins in 0..q-1, uint8 [L, L], from numpy's PCG64."""
     rng = np.random.Generator(np.random.PCG64(seed))
