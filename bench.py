@@ -314,6 +314,38 @@ def batched_vs_plain(n_replicas: int, sweeps: int, tile_rows: int) -> dict:
             "speedup": t_plain / t_batch, "identical_results": bool(same)}
 
 
+def small_mixes(sweeps: int) -> list:
+    """Batches of many small lattices (q = 2 at K_c, random start): 1024 of
+    L = 64, 256 of L = 128, 64 of L = 256 -- the same number of sites each,
+    swept as one batch (one launch per phase, HIP graph): flips/ns and
+    microseconds per batch sweep."""
+    import torch
+    from paper_1208_2080_amd import binding
+    from paper_1208_2080_amd import workloads as wl
+    out = []
+    for n, L in ((1024, 64), (256, 128), (64, 256)):
+        reps = [{"L": L, "q": 2, "K": wl.critical_coupling(2), "seed": 5000 + r, "random_start": True}
+                for r in range(n)]
+        # the default (whole lattice in LDS where L <= 128) and 64-row tiles
+        for ty in ((0, 64) if L <= binding.WHOLE_LMAX else (0,)):
+            b = binding.Batch(reps, obs_capacity=2, tile_rows=ty)
+            b.sweep_all(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            done = 0
+            while done < sweeps:
+                k = min(100, sweeps - done)
+                b.sweep_all(k)
+                done += k
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            b.close()
+            path = "whole" if (ty == 0 and L <= binding.WHOLE_LMAX) else "tiles64"
+            out.append({"replicas": n, "L": L, "path": path, "sweeps": sweeps,
+                        "flips_per_ns": n * L * L * sweeps / (wall * 1e9), "us_per_batch_sweep": wall * 1e6 / sweeps})
+    return out
+
+
 def label_equivalence(lat, sweeps: int, per_launch_ms: dict) -> dict:
     """The paper's labelling (iterated label equivalence: scan + analysis under
     a host loop) on the bonds of `sweeps` further sweeps of the bench lattice,
@@ -499,6 +531,7 @@ def main():
         out["L65536"] = huge_lattices(2, args.huge)
     if args.small:
         out["L64"] = small_lattice(args.small)
+        out["small_lattice_batches"] = small_mixes(1000)
     if args.xy:
         out["xy_L16384"] = xy_lattice(5, args.xy, not args.no_cpu_baseline)
     if args.serve:

@@ -60,9 +60,19 @@ typedef struct sw_params {
     uint32_t init;         /* 0 = cold start (all spins 0), 1 = random start */
     uint32_t obs_capacity; /* sweeps of observables kept in the device ring;
                               0 = no measurement ("update only"), else >= 2 */
-    uint32_t tile_rows;    /* labelling tile height: 0 (default), 32, 64 or 128 */
+    uint32_t tile_rows;    /* labelling tile height: 32, 64 or 128; SW_TILE_WHOLE
+                              (L <= 128, no cluster sums): the whole lattice in
+                              one workgroup's LDS, many sweeps per launch; 0
+                              (default): SW_TILE_WHOLE where it applies, else 64 */
     uint32_t flags;        /* 0, or SW_CLUSTER_SUMS */
 } sw_params;
+
+/* tile_rows: sweep the lattice whole in one workgroup's local memory (bonds,
+ * union-find labels and new states of every sweep without a kernel launch per
+ * sweep or global traffic between sweeps; the same random streams and cluster
+ * keys as the tile kernels, so the same results).  Labels and bond words of a
+ * call's last sweep are written for sw_read_labels / sw_read_bonds as usual. */
+#define SW_TILE_WHOLE 1u
 
 /* flags: also measure, for every sweep, the cluster-size sums of the sweep's
  * clusters (sw_cluster_sums).  Needs L <= 32768 and obs_capacity > 0. */
@@ -220,9 +230,11 @@ int sw_batch_destroy(sw_batch* b);
  * and the tile-edge merge (the two stages of Sec. 3); spins, labels and
  * observables do not depend on it (cluster roots are smallest site indices and
  * every draw is keyed by site and sweep), so it is a pure performance choice.
- * For each of the n_candidates (1..8) heights in candidates[] (each 32, 64 or
- * 128), this initialises the n replicas params[] (their own tile_rows is
- * ignored) in dev_ws, runs `sweeps` (1..4096) untimed sweeps of every replica,
+ * For each of the n_candidates (1..8) heights in candidates[] (each 32, 64,
+ * 128, SW_TILE_WHOLE -- every replica swept whole in LDS, which needs
+ * L <= 128 and no cluster sums -- or 0, the default rule: whole where that
+ * applies, 64 elsewhere), this initialises the n replicas params[] (their own
+ * tile_rows is ignored) in dev_ws, runs `sweeps` (1..4096) untimed sweeps of every replica,
  * then times `sweeps` more with HIP events on hip_stream, and writes the
  * fastest height into *tile_rows and, if ms_per_sweep is not NULL, the measured
  * milliseconds per sweep of candidate c into ms_per_sweep[c].  dev_ws must hold

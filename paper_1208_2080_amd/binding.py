@@ -33,6 +33,8 @@ class SwParams(ctypes.Structure):
 
 
 SW_CLUSTER_SUMS = 1
+SW_TILE_WHOLE = 1          # tile_rows: the whole lattice (L <= 128) in one workgroup's LDS
+WHOLE_LMAX = 128
 
 
 class SwXYParams(ctypes.Structure):
@@ -399,11 +401,19 @@ def _batch_bytes(arr) -> int:
 TILE_HEIGHTS = (32, 64, 128)
 
 
-def autotune(replicas, obs_capacity: int = 64, candidates=TILE_HEIGHTS, sweeps: int = 8, device=None,
+def tile_candidates(replicas):
+    """The autotuner's default candidates: the default rule (0), the three tile
+    heights, and SW_TILE_WHOLE when every replica can be swept whole."""
+    whole = all(r["L"] <= WHOLE_LMAX and not r.get("cluster_sums", False) for r in replicas)
+    return (0,) + TILE_HEIGHTS + ((SW_TILE_WHOLE,) if whole else ())
+
+
+def autotune(replicas, obs_capacity: int = 64, candidates=None, sweeps: int = 8, device=None,
              stream=None):
     """Pick the fastest labelling tile height for this set of replicas (the
     library times each candidate); returns (height, {height: ms per sweep})."""
     replicas = [dict(r) for r in replicas]
+    candidates = tile_candidates(replicas) if candidates is None else tuple(candidates)
     cands = (ctypes.c_uint32 * len(candidates))(*[int(c) for c in candidates])
     nbytes = max(_batch_bytes(_replica_params(replicas, obs_capacity, int(c))) for c in candidates)
     device = torch.device("cuda", 0) if device is None else torch.device(device)

@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libswmi.so")
-SOURCES = ["sw_kernels.hip", "sw_xy.hip", "sw_ablation.hip", "sw_capi.cpp"]
+SOURCES = ["sw_kernels.hip", "sw_xy.hip", "sw_whole.hip", "sw_ablation.hip", "sw_capi.cpp"]
 ARCH = "gfx950"
 
 # hipcc flags for every HIP translation unit: gfx950 only, no packed-FP32 ops.

@@ -54,6 +54,7 @@ struct Geometry {
     uint64_t thr;
     bool csum;   // cluster-size sums measured
     bool xy = false;         // an XY lattice (q unused)
+    bool whole = false;      // swept whole in one workgroup's LDS (k_whole); ty is the bond-word layout
     uint32_t dir_bits = 0;   // XY: bits of the direction draw kept
     double K = 0.0;          // XY: the coupling
 };
@@ -75,8 +76,9 @@ int check_common(uint32_t L, uint32_t obs_capacity, uint32_t tile_rows, Geometry
     if (L < 2 || L > 65536) return fail(SW_EINVAL, "L = %u outside 2..65536", L);
     if (obs_capacity == 1) return fail(SW_EINVAL, "obs_capacity must be 0 or >= 2");
     if (obs_capacity > (1u << 28)) return fail(SW_EINVAL, "obs_capacity too large");
-    const uint32_t ty = tile_rows ? tile_rows : DEFAULT_TY;
-    if (ty != 32 && ty != 64 && ty != 128) return fail(SW_EINVAL, "tile_rows must be 0, 32, 64 or 128");
+    const uint32_t ty = (tile_rows == 0 || tile_rows == SW_TILE_WHOLE) ? DEFAULT_TY : tile_rows;
+    if (ty != 32 && ty != 64 && ty != 128)
+        return fail(SW_EINVAL, "tile_rows must be 0, SW_TILE_WHOLE, 32, 64 or 128");
     g->L = L;
     g->W = (L + 63) / 64;
     g->ty = ty;
@@ -95,6 +97,7 @@ int check_xy_params(const sw_xy_params* p, Geometry* g)
     if (p->dir_bits < 1 || p->dir_bits > 32) return fail(SW_EINVAL, "dir_bits = %u outside 1..32", p->dir_bits);
     if (p->init > 1) return fail(SW_EINVAL, "init must be 0 (cold) or 1 (random)");
     if (p->reserved) return fail(SW_EINVAL, "reserved must be 0");
+    if (p->tile_rows == SW_TILE_WHOLE) return fail(SW_EINVAL, "SW_TILE_WHOLE sweeps Potts lattices only");
     const int rc = check_common(p->L, p->obs_capacity, p->tile_rows, g);
     if (rc) return rc;
     g->q = 0;
@@ -121,6 +124,10 @@ int check_params(const sw_params* p, Geometry* g)
     g->q = p->q;
     g->thr = threshold_of(p->K);
     g->csum = (p->flags & SW_CLUSTER_SUMS) != 0;
+    const bool fits = p->L <= WHOLE_LMAX && !g->csum;
+    if (p->tile_rows == SW_TILE_WHOLE && !fits)
+        return fail(SW_EINVAL, "SW_TILE_WHOLE needs L <= %u and no cluster sums", WHOLE_LMAX);
+    g->whole = p->tile_rows == SW_TILE_WHOLE || (p->tile_rows == 0 && fits);
     return SW_OK;
 }
 
@@ -479,11 +486,29 @@ int sw_init(const sw_params* p, void* dev_ws, size_t ws_bytes, void* hip_stream,
     return create_lattice(g, p->seed, p->init, dev_ws, ws_bytes, hip_stream, out);
 }
 
+// n sweeps of a lattice swept whole, in launches of at most WHOLE_CHUNK
+// sweeps; the last sweep's labels and bond words are written.
+constexpr uint32_t WHOLE_CHUNK = 4096;
+
+static int whole_sweeps(sw_lattice* h, uint32_t n)
+{
+    for (uint32_t done = 0; done < n;) {
+        const uint32_t k = std::min(WHOLE_CHUNK, n - done);
+        HIP_TRY(launch_whole(h->d_desc, nullptr, 1, h->g.L, 0, k, nullptr, 1u, h->g.ty, h->stream));
+        done += k;
+    }
+    h->done += n;
+    h->have_sweep = true;
+    h->labels_resolved = true;   // k_whole writes smallest site indices
+    return SW_OK;
+}
+
 int sw_sweep(sw_lattice* h, uint32_t n_sweeps)
 {
     if (!h) return fail(SW_EINVAL, "handle is NULL");
     if (n_sweeps == 0) return SW_OK;
     if ((uint64_t)h->done + n_sweeps > 0xFFFFFFFFull) return fail(SW_ESTATE, "sweep counter would overflow");
+    if (h->g.whole) return whole_sweeps(h, n_sweeps);
     const Work w{h->d_desc, nullptr, h->g.ntiles, h->g.ty, h->stream, h->g.csum, h->g.xy};
     // the legacy NULL stream cannot be captured: launch directly
     const int rc = h->stream ? run_steps(h->graphs, w, n_sweeps, h->g.cap != 0, h->d_desc, 1)
@@ -502,6 +527,23 @@ int sw_sweep_profiled(sw_lattice* h, uint32_t n_sweeps, double* phase_ms)
     if (n_sweeps == 0) return SW_OK;
     if ((uint64_t)h->done + n_sweeps > 0xFFFFFFFFull) return fail(SW_ESTATE, "sweep counter would overflow");
     if (n_sweeps > (1u << 20)) return fail(SW_EINVAL, "profile at most 2^20 sweeps per call");
+    if (h->g.whole) {
+        // one kernel does every phase: its time is the bond-and-label phase
+        hipEvent_t e[2] = {nullptr, nullptr};
+        for (auto& x : e) HIP_TRY(hipEventCreate(&x));
+        int rc = SW_OK;
+        if (hipEventRecord(e[0], h->stream) != hipSuccess) rc = fail(SW_EHIP, "hipEventRecord failed");
+        if (rc == SW_OK) rc = whole_sweeps(h, n_sweeps);
+        if (rc == SW_OK && hipEventRecord(e[1], h->stream) != hipSuccess) rc = fail(SW_EHIP, "hipEventRecord failed");
+        if (rc == SW_OK && hipEventSynchronize(e[1]) != hipSuccess) rc = fail(SW_EHIP, "hipEventSynchronize failed");
+        float ms = 0.f;
+        if (rc == SW_OK && hipEventElapsedTime(&ms, e[0], e[1]) != hipSuccess)
+            rc = fail(SW_EHIP, "hipEventElapsedTime failed");
+        for (auto& x : e) (void)hipEventDestroy(x);
+        if (rc) return rc;
+        phase_ms[0] = phase_ms[4] = ms;
+        return check_device_error(h->desc, h->stream);
+    }
     std::vector<hipEvent_t> ev(4 * (size_t)n_sweeps + 2, nullptr);
     int rc = SW_OK;
     // timing-only events: no system-scope fence (cache write-back) at each one
@@ -812,12 +854,16 @@ struct sw_batch {
     std::vector<uint32_t> map_order;  // replica order of the uploaded map
     StepGraphs steps;                            // captured sweeps of every replica (sweep_all)
     bool csum = false;                           // some replica measures cluster-size sums
+    // replicas swept whole (k_whole): device list, L <= 64 first, then the rest
+    uint32_t* d_list = nullptr;
+    uint32_t n_whole64 = 0, n_whole128 = 0;
+    size_t tile_tiles = 0;                       // tiles of the replicas swept by tiles
 };
 
 namespace {
 
 struct BatchLayout {
-    size_t descs, map, nvec, header;
+    size_t descs, map, nvec, list, header;
     std::vector<size_t> off;
     std::vector<Geometry> g;
     std::vector<Carve> c;
@@ -849,6 +895,8 @@ int batch_layout(const sw_params* params, uint32_t n, BatchLayout* out)
     off = align_up(off + sizeof(WorkItem) * b.total_tiles);
     b.nvec = off;
     off = align_up(off + sizeof(uint32_t) * n);
+    b.list = off;
+    off = align_up(off + sizeof(uint32_t) * n);
     b.header = off;
     for (uint32_t r = 0; r < n; ++r) {
         b.off[r] = off;
@@ -866,7 +914,7 @@ int upload_map(sw_batch* b, const uint32_t* n_each, uint32_t kmax, std::vector<u
 {
     std::vector<uint32_t> order;
     for (uint32_t r = 0; r < b->n; ++r)
-        if (n_each[r]) order.push_back(r);
+        if (n_each[r] && !b->g[r].whole) order.push_back(r);
     std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t c) { return n_each[a] > n_each[c]; });
     if (order != b->map_order || b->h_map.empty()) {
         b->h_map.clear();
@@ -894,16 +942,33 @@ int upload_map(sw_batch* b, const uint32_t* n_each, uint32_t kmax, std::vector<u
     return SW_OK;
 }
 
+// The replicas swept whole: n_each[r] (or n_uniform) sweeps from counter + k0,
+// counters left for the caller to advance.
+int batch_whole(sw_batch* b, uint32_t k0, uint32_t n_uniform, const uint32_t* d_n_each)
+{
+    HIP_TRY(launch_whole(b->d_descs, b->d_list, b->n_whole64, 64, k0, n_uniform, d_n_each, 2u, b->ty, b->stream));
+    HIP_TRY(launch_whole(b->d_descs, b->d_list + b->n_whole64, b->n_whole128, WHOLE_LMAX, k0, n_uniform, d_n_each, 2u,
+                         b->ty, b->stream));
+    return SW_OK;
+}
+
 int batch_enqueue(sw_batch* b, const uint32_t* n_each)
 {
-    uint32_t kmax = 0;
-    for (uint32_t r = 0; r < b->n; ++r) kmax = std::max(kmax, n_each[r]);
-    if (kmax == 0) return SW_OK;
-    std::vector<uint32_t> prefix;
-    int rc = upload_map(b, n_each, kmax, &prefix);
-    if (rc) return rc;
+    uint32_t kmax = 0, kall = 0;
+    for (uint32_t r = 0; r < b->n; ++r) {
+        kall = std::max(kall, n_each[r]);
+        if (!b->g[r].whole) kmax = std::max(kmax, n_each[r]);
+    }
+    if (kall == 0) return SW_OK;
     b->h_n.assign(n_each, n_each + b->n);
     HIP_TRY(hipMemcpyAsync(b->d_n, b->h_n.data(), b->n * sizeof(uint32_t), hipMemcpyHostToDevice, b->stream));
+    int rc = batch_whole(b, 0, 0, b->d_n);
+    if (rc) return rc;
+    std::vector<uint32_t> prefix;
+    if (kmax) {
+        rc = upload_map(b, n_each, kmax, &prefix);
+        if (rc) return rc;
+    }
     for (uint32_t k = 0; k < kmax; ++k) {
         const Work w{b->d_descs, b->d_map, prefix[k], b->ty, b->stream, b->csum};
         HIP_TRY(launch_bond_label(w, k, k > 0 ? 1u : 0u));
@@ -911,8 +976,10 @@ int batch_enqueue(sw_batch* b, const uint32_t* n_each)
         HIP_TRY(launch_flip(w, k));
         if (w.cluster) HIP_TRY(launch_cluster_sums(w, k));
     }
-    const Work w0{b->d_descs, b->d_map, prefix[0], b->ty, b->stream};
-    HIP_TRY(launch_measure_each(w0, b->d_n));
+    if (kmax) {
+        const Work w0{b->d_descs, b->d_map, prefix[0], b->ty, b->stream};
+        HIP_TRY(launch_measure_each(w0, b->d_n));
+    }
     HIP_TRY(launch_bump(b->d_descs, b->n, b->d_n, 0, b->stream));
     return SW_OK;
 }
@@ -965,6 +1032,16 @@ int sw_batch_init(const sw_params* params, uint32_t n, void* dev_ws, size_t ws_b
     b->d_descs = reinterpret_cast<LatDesc*>(b->base + lay.descs);
     b->d_map = reinterpret_cast<WorkItem*>(b->base + lay.map);
     b->d_n = reinterpret_cast<uint32_t*>(b->base + lay.nvec);
+    b->d_list = reinterpret_cast<uint32_t*>(b->base + lay.list);
+    std::vector<uint32_t> list;
+    for (uint32_t r = 0; r < n; ++r)
+        if (lay.g[r].whole && lay.g[r].L <= 64) list.push_back(r);
+    b->n_whole64 = (uint32_t)list.size();
+    for (uint32_t r = 0; r < n; ++r)
+        if (lay.g[r].whole && lay.g[r].L > 64) list.push_back(r);
+    b->n_whole128 = (uint32_t)list.size() - b->n_whole64;
+    for (uint32_t r = 0; r < n; ++r)
+        if (!lay.g[r].whole) b->tile_tiles += lay.g[r].ntiles;
     b->desc.resize(n);
     for (uint32_t r = 0; r < n; ++r) b->csum = b->csum || b->g[r].csum;
     for (uint32_t r = 0; r < n; ++r) {
@@ -976,6 +1053,9 @@ int sw_batch_init(const sw_params* params, uint32_t n, void* dev_ws, size_t ws_b
     }
     auto run = [&]() -> int {
         HIP_TRY(hipMemcpyAsync(b->d_descs, b->desc.data(), sizeof(LatDesc) * n, hipMemcpyHostToDevice, b->stream));
+        if (!list.empty())
+            HIP_TRY(hipMemcpyAsync(b->d_list, list.data(), list.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                                   b->stream));
         for (uint32_t r = 0; r < n; ++r) {
             char* base = b->base + b->off[r];
             HIP_TRY(hipMemsetAsync(base + b->c[r].state, 0, sizeof(DevState), b->stream));
@@ -1027,15 +1107,32 @@ int sw_batch_sweep_all(sw_batch* b, uint32_t n_sweeps)
         for (uint32_t r = 0; r < b->n; ++r) b->done[r] += n_sweeps;
         return SW_OK;
     }
-    // the captured steps bake in the work map of "every replica"; make sure it is the one uploaded
-    std::vector<uint32_t> order(b->n);
-    for (uint32_t r = 0; r < b->n; ++r) order[r] = r;
+    if (b->n_whole64 + b->n_whole128) {
+        // the replicas swept whole first, in launches of at most WHOLE_CHUNK
+        // sweeps; their counters advance with everyone's below
+        for (uint32_t done = 0; done < n_sweeps;) {
+            const uint32_t k = std::min(WHOLE_CHUNK, n_sweeps - done);
+            const int rc = batch_whole(b, done, k, nullptr);
+            if (rc) return rc;
+            done += k;
+        }
+        if (b->tile_tiles == 0) {
+            HIP_TRY(launch_bump(b->d_descs, b->n, nullptr, n_sweeps, b->stream));
+            for (uint32_t r = 0; r < b->n; ++r) b->done[r] += n_sweeps;
+            return SW_OK;
+        }
+    }
+    // the captured steps bake in the work map of every replica swept by
+    // tiles; make sure it is the one uploaded
+    std::vector<uint32_t> order;
+    for (uint32_t r = 0; r < b->n; ++r)
+        if (!b->g[r].whole) order.push_back(r);
     if (b->map_order != order || b->h_map.empty()) {
         std::vector<uint32_t> prefix;
         int rc = upload_map(b, all.data(), 1, &prefix);
         if (rc) return rc;
     }
-    const Work w{b->d_descs, b->d_map, (uint32_t)b->total_tiles, b->ty, b->stream, b->csum};
+    const Work w{b->d_descs, b->d_map, (uint32_t)b->tile_tiles, b->ty, b->stream, b->csum};
     // replicas without a ring skip the measurements inside the kernels
     const int rc = run_steps(b->steps, w, n_sweeps, true, b->d_descs, b->n);
     if (rc) return rc;
@@ -1113,7 +1210,8 @@ int sw_batch_autotune(const sw_params* params, uint32_t n, const uint32_t* candi
     // every candidate is checked (and its workspace sized) before the first launch
     for (uint32_t c = 0; c < n_candidates; ++c) {
         const uint32_t ty = candidates[c];
-        if (ty != 32 && ty != 64 && ty != 128) return fail(SW_EINVAL, "candidate tile height %u is not 32, 64 or 128", ty);
+        if (ty != 0 && ty != SW_TILE_WHOLE && ty != 32 && ty != 64 && ty != 128)
+            return fail(SW_EINVAL, "candidate tile height %u is not 0, SW_TILE_WHOLE, 32, 64 or 128", ty);
         for (auto& pr : p) pr.tile_rows = ty;
         size_t need = 0;
         const int rc = sw_batch_workspace_bytes(p.data(), n, &need);

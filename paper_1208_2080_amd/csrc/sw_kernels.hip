@@ -28,7 +28,6 @@ namespace {
 // themselves).  Every pointer walk steps only to strictly smaller indices, so
 // it ends even in a corrupted forest, and union retries carry caps; a forest
 // that breaks the invariant sets the error flag instead of spinning.
-constexpr uint32_t LDS_CAP = 1u << 15;     // cap of union retries in LDS (> sites of a tile)
 constexpr uint32_t UNITE_CAP = 1u << 12;   // cap of union retries in the global forest
 constexpr uint32_t SPW = TX + 4;           // LDS row stride of staged spins (bytes)
 
@@ -56,101 +55,6 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
 __device__ __forceinline__ uint32_t swap_pair(uint32_t v)
 {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-}
-
-// ------------------------------------------------------- LDS union-find
-// P holds, for every site of the tile, a tile-local index (16 bits: a tile has
-// at most 2^13 sites) that is never larger than its own; roots point at
-// themselves.  Entries only ever decrease (unions hook the larger root under
-// the smaller one with a minimum; finds point nodes at their grandparents),
-// so every walk that steps only to smaller indices ends.  A walk that stops at
-// a node pointing to a larger index has met a corrupted forest and sets `bad`,
-// which the kernel reports.  16-bit entries halve the forest's LDS, so more
-// workgroups fit a CU; the minimum (there is no 16-bit LDS minimum) is a
-// compare-and-swap on the entry's 32-bit word.
-__device__ __forceinline__ uint32_t lds_ld(uint32_t* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_st(uint32_t* p, uint32_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ uint32_t lds_ld(uint16_t* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void lds_st(uint16_t* p, uint32_t v)
-{
-    __hip_atomic_store(p, (uint16_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
-// Entry i of P set to `desired` if it holds `expect` (as a compare-and-swap
-// would); returns the entry's value before.  A failed 32-bit swap means the
-// word changed, so some lane made progress.
-__device__ __forceinline__ uint32_t lds_cas16(uint16_t* P, uint32_t i, uint32_t expect, uint32_t desired, bool& bad)
-{
-    uint32_t* const w = reinterpret_cast<uint32_t*>(P) + (i >> 1);
-    const uint32_t sh = (i & 1u) * 16u;
-    uint32_t cur = lds_ld(w);
-    for (uint32_t it = 0; it < LDS_CAP; ++it) {
-        const uint32_t old = (cur >> sh) & 0xFFFFu;
-        if (old != expect) return old;
-        const uint32_t seen = atomicCAS(w, cur, (cur & ~(0xFFFFu << sh)) | (desired << sh));
-        if (seen == cur) return old;
-        cur = seen;
-    }
-    bad = true;
-    return expect;
-}
-
-// min(P[i], v) into entry i; returns the entry's value before.
-__device__ __forceinline__ uint32_t lds_min16(uint16_t* P, uint32_t i, uint32_t v, bool& bad)
-{
-    uint32_t* const w = reinterpret_cast<uint32_t*>(P) + (i >> 1);
-    const uint32_t sh = (i & 1u) * 16u;
-    uint32_t cur = lds_ld(w);
-    for (uint32_t it = 0; it < LDS_CAP; ++it) {
-        const uint32_t old = (cur >> sh) & 0xFFFFu;
-        if (old <= v) return old;
-        const uint32_t seen = atomicCAS(w, cur, (cur & ~(0xFFFFu << sh)) | (v << sh));
-        if (seen == cur) return old;
-        cur = seen;
-    }
-    bad = true;
-    return v;
-}
-
-// Root of x while unions may still run, with path splitting: every visited
-// node is pointed at its grandparent (a stored value is always an ancestor,
-// so races with other finds and hooks are benign).
-__device__ __forceinline__ uint32_t lds_find(uint16_t* P, uint32_t x, bool& bad)
-{
-    uint32_t p = lds_ld(&P[x]);
-    while (p < x) {
-        const uint32_t gp = lds_ld(&P[p]);
-        lds_st(&P[x], gp);
-        x = p;
-        p = gp;
-    }
-    bad |= p != x;
-    return x;
-}
-
-__device__ void lds_union(uint16_t* P, uint32_t a, uint32_t b, bool& bad)
-{
-    for (uint32_t it = 0; it < LDS_CAP; ++it) {
-        a = lds_find(P, a, bad);
-        b = lds_find(P, b, bad);
-        if (a == b) return;
-        const uint32_t hi = max(a, b), lo = min(a, b);
-        const uint32_t old = lds_min16(P, hi, lo, bad);
-        if (old == hi) return;
-        // hi was hooked meanwhile: join its new parent with lo instead
-        a = old;
-        b = lo;
-    }
-    bad = true;
 }
 
 // ------------------------------------------------------ edge forest (global)
@@ -1252,10 +1156,15 @@ __global__ __launch_bounds__(256) void k_ring_sum(const int64_t* ring, int64_t* 
     const uint32_t rec = i / W, w = i - rec * W;
     const uint32_t slot = (uint32_t)(((uint64_t)slot0 + rec) % slots);
     const size_t R = stride;
-    const gptr<const int64_t> base = glb(ring) + (size_t)slot * NCOPY * R + w;
+    const gptr<const int64_t> copy0 = glb(ring) + (size_t)slot * NCOPY * R;
+    const gptr<const int64_t> base = copy0 + w;
     int64_t sum = 0;
+    if (copy0[W] != 0) {
+        sum = base[0];   // the whole record is in copy 0
+    } else {
 #pragma unroll 8
-    for (uint32_t c = 0; c < NCOPY; ++c) sum += base[(size_t)c * R];
+        for (uint32_t c = 0; c < NCOPY; ++c) sum += base[(size_t)c * R];
+    }
     glb(out)[i] = sum;
 }
 

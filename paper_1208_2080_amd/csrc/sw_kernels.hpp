@@ -40,6 +40,14 @@ hipError_t launch_xy_bonds(const Work& w, uint32_t k, uint32_t flags);
 hipError_t launch_label_preset(const Work& w);
 hipError_t launch_flip_xy(const Work& w, uint32_t k);
 hipError_t launch_xy_init(const LatDesc* descs, size_t N, uint32_t random_start, hipStream_t s);
+// Lattices of L <= WHOLE_LMAX swept whole in one workgroup each (descs[list[b]]
+// for workgroup b, or descs[b] without a list), n_each[lattice] (or n_uniform)
+// sweeps each from sweep counter + k0; lmax: the largest L among them.  flags
+// bit 0: also write the last sweep's labels (smallest site indices) and bond
+// words (tile-major, ty rows per tile); bit 1: leave the sweep counters (else
+// set past the last sweep).
+hipError_t launch_whole(const LatDesc* descs, const uint32_t* list, uint32_t count, uint32_t lmax, uint32_t k0,
+                        uint32_t n_uniform, const uint32_t* n_each, uint32_t flags, uint32_t ty, hipStream_t s);
 // Labels of the last sweep resolved in place to smallest site indices.
 hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, uint32_t ntiles, uint32_t ty, hipStream_t s);
 // Sum the NCOPY partial copies of n ring records of `words` words (copies

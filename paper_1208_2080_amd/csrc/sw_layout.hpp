@@ -43,6 +43,7 @@ constexpr uint32_t ROOT = 0x80000000u;     // label of a tile-local root
 constexpr uint32_t NOSLOT = 0x7FFFu;       // root of a cluster inside its tile
 constexpr uint32_t ROOT16 = 0x8000u;       // tile-local root's tag in 16-bit entries
 constexpr uint32_t INVALID = 0xFFFFFFFFu;
+constexpr uint32_t WHOLE_LMAX = 128;       // largest L swept whole in one workgroup's LDS
 
 // Boundary record of a tile with TY rows: 8 uint32 words, then uint16 slots
 // (edge-forest nodes of the tile-local roots) of its edge sites:
@@ -64,16 +65,23 @@ __host__ __device__ constexpr uint32_t nslot(uint32_t ty) { return 2u * TX + 2u 
 __host__ __device__ constexpr uint32_t ring_words(uint32_t q) { return q + 4u; }
 __host__ __device__ constexpr uint32_t cs_word(uint32_t q) { return q + 1u; }
 
-// int64 words between partial copies of a ring record: the record rounded up
-// to whole 256-byte blocks, so no two copies share a cache line.
-__host__ __device__ constexpr uint32_t ring_stride(uint32_t q) { return (ring_words(q) + 31u) & ~31u; }
+// int64 words between partial copies of a ring record: the record and one
+// more word (the whole-record flag below) rounded up to whole 256-byte blocks,
+// so no two copies share a cache line.
+__host__ __device__ constexpr uint32_t ring_stride(uint32_t q) { return (ring_words(q) + 1u + 31u) & ~31u; }
+
+// Word ring_words(q) (XY_WORDS for an XY record) of partial copy 0 is the
+// whole-record flag: nonzero when copy 0 holds the complete record (written by
+// the workgroup that sweeps a whole lattice), so the other copies, which may
+// hold stale sums of an older use of the slot, are not added.  Clearing a
+// record clears the flag with it.
 
 // Ring record of an XY lattice: n_active, then the sums over sites of
 // cos(theta_i - theta_{i+x}), cos(theta_i - theta_{i+y}), sin of the same two
 // differences, cos theta_i and sin theta_i, each term rounded to a multiple of
 // 2^-30 (so the sums are exact integers, whatever the order of addition).
 constexpr uint32_t XY_WORDS = 7;
-constexpr uint32_t XY_STRIDE = (XY_WORDS + 31u) & ~31u;
+constexpr uint32_t XY_STRIDE = (XY_WORDS + 1u + 31u) & ~31u;
 
 struct DevState {
     uint32_t err;          // nonzero: a safety cap tripped

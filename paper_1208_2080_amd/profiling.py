@@ -29,7 +29,7 @@ COPY_BYTES = 1 << 30
 
 def kernel_source_digest() -> str:
     h = hashlib.sha256()
-    for name in ("sw_kernels.hip", "sw_xy.hip", "sw_tile.hpp", "sw_device.hpp", "sw_layout.hpp"):
+    for name in ("sw_kernels.hip", "sw_xy.hip", "sw_whole.hip", "sw_tile.hpp", "sw_device.hpp", "sw_layout.hpp"):
         with open(os.path.join(HERE, "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

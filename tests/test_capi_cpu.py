@@ -199,3 +199,13 @@ def test_xy_derived_matches_oracle_values():
         assert abs(got["Y"] - ref["Y"]) <= bound * (1 + 1e-6) + 1e-15
     with pytest.raises(binding.SwError):
         binding.xy_derived(np.array([0, 2**62, 0, 0, 0, 0, 0]), 16, 1.0)    # |Ex| > N
+
+
+def test_whole_lattice_tile_rows():
+    assert _ws(128, ty=binding.SW_TILE_WHOLE) > 0
+    assert _ws(129, ty=binding.SW_TILE_WHOLE) == 0
+    p = binding.make_params(64, 2, 1.0, obs_capacity=4, tile_rows=binding.SW_TILE_WHOLE, cluster_sums=True)
+    assert binding.lib().sw_workspace_bytes(ctypes.byref(p)) == 0
+    assert _ws(64, ty=binding.SW_TILE_WHOLE) == _ws(64)          # the same workspace layout
+    assert _ws(64, ty=5) == 0
+    assert _xy_ws(64, ty=binding.SW_TILE_WHOLE) == 0

@@ -77,11 +77,13 @@ def test_batch_sweep_all_graph_reuse_matches_oracle():
 def test_autotuned_batch_matches_oracle():
     say("batch autotune")
     best, ms = binding.autotune(MIX, obs_capacity=32, sweeps=4)
-    assert best in binding.TILE_HEIGHTS
-    assert set(ms) == set(binding.TILE_HEIGHTS) and all(v > 0 for v in ms.values())
+    cands = binding.tile_candidates(MIX)
+    assert binding.SW_TILE_WHOLE not in cands          # MIX has lattices larger than 128
+    assert best in cands
+    assert set(ms) == set(cands) and all(v > 0 for v in ms.values())
     assert ms[best] == min(ms.values())
     b = binding.Batch(MIX, obs_capacity=32, tile_rows="auto")
-    assert b.tile_rows in binding.TILE_HEIGHTS and b.tuned_ms[b.tile_rows] == min(b.tuned_ms.values())
+    assert b.tile_rows in cands and b.tuned_ms[b.tile_rows] == min(b.tuned_ms.values())
     refs = [oracle.OracleLattice(r["L"], r["q"], r["K"], r["seed"], r.get("random_start", True)) for r in MIX]
     b.sweep_all(5)
     for r, ref in enumerate(refs):

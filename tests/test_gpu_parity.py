@@ -187,7 +187,8 @@ def test_corrupted_label_forest_is_reported_not_walked():
     # walk steps only to smaller indices, so it ends).  The corruption is
     # written from the host into the workspace, between a sweep and the read.
     L = 16
-    lat = binding.Lattice(L, 2, wl.critical_coupling(2), seed=3, obs_capacity=4)
+    # the tile kernels' label format (a small lattice is otherwise swept whole)
+    lat = binding.Lattice(L, 2, wl.critical_coupling(2), seed=3, obs_capacity=4, tile_rows=64)
     lat.sweep(1)
     # the labels follow the state (256 B), the descriptor (one 256-byte block)
     # and the spins (L*L bytes, 256-aligned) in the workspace
