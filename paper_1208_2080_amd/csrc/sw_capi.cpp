@@ -196,6 +196,7 @@ LatDesc make_desc(const Geometry& g, uint64_t seed, char* base, const Carve& c)
         d.s = reinterpret_cast<uint8_t*>(base + c.spins);
     }
     d.lab = reinterpret_cast<uint32_t*>(base + c.lab);
+    d.tlab = reinterpret_cast<uint16_t*>(base + c.lab + (size_t)g.N * 2);
     d.bonds = reinterpret_cast<uint64_t*>(base + c.bonds);
     d.edges = reinterpret_cast<uint32_t*>(base + c.edges);
     d.nodes = reinterpret_cast<uint64_t*>(base + c.nodes);
@@ -252,7 +253,7 @@ struct sw_lattice {
     uint32_t done;           // sweeps done since init (index of the next sweep)
     uint32_t first_obs;      // first sweep whose observables exist
     bool have_sweep;         // labels and bonds of a sweep are in place
-    bool labels_resolved;    // the labels hold smallest site indices (after sw_read_labels)
+    bool labels_resolved;    // the label region holds all N smallest site indices (a whole-lattice sweep)
     StepGraphs graphs;       // captured sweeps (streams other than the legacy NULL stream)
 };
 
@@ -674,11 +675,19 @@ int sw_read_labels(sw_lattice* h, uint32_t* host_out)
 {
     if (!h || !host_out) return fail(SW_EINVAL, "NULL argument");
     if (!h->have_sweep) return fail(SW_ESTATE, "no sweep since init / load");
-    if (!h->labels_resolved) {
-        HIP_TRY(launch_resolve(h->d_desc, 0, h->g.ntiles, h->g.ty, h->stream));
-        h->labels_resolved = true;
+    const Geometry& g = h->g;
+    if (h->labels_resolved) {
+        HIP_TRY(hipMemcpyAsync(host_out, h->desc.lab, g.N * 4, hipMemcpyDeviceToHost, h->stream));
+        return check_device_error(h->desc, h->stream);
     }
-    HIP_TRY(hipMemcpyAsync(host_out, h->desc.lab, h->g.N * 4, hipMemcpyDeviceToHost, h->stream));
+    // resolved in bands of at most N/2 sites, below the tile labels they read
+    const uint32_t band = std::max(1u, g.L / 2);
+    for (uint32_t ya = 0; ya < g.L; ya += band) {
+        const uint32_t yb = std::min(g.L, ya + band);
+        HIP_TRY(launch_resolve(h->d_desc, 0, g.ntiles, g.ty, ya, yb, h->stream));
+        HIP_TRY(hipMemcpyAsync(host_out + (size_t)ya * g.L, h->desc.lab, (size_t)(yb - ya) * g.L * 4,
+                               hipMemcpyDeviceToHost, h->stream));
+    }
     return check_device_error(h->desc, h->stream);
 }
 

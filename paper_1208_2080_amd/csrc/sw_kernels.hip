@@ -156,6 +156,34 @@ __device__ void n_find2(gptr<uint64_t> nodes, uint32_t n, uint32_t& a, uint64_t&
     bad = true;
 }
 
+// Roots of M nodes x[m] (words w[m] already loaded; only the chains whose bit
+// is set in `live` are walked), one level of every unfinished chain per step so
+// that the loads of all chains overlap.
+template <int M>
+__device__ void n_find_m(gptr<uint64_t> nodes, uint32_t n, uint32_t (&x)[M], uint64_t (&w)[M], uint32_t live,
+                         bool& bad)
+{
+    for (uint32_t it = 0; it < UNITE_CAP; ++it) {
+        bool done = true;
+        uint64_t wp[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const bool walk = ((live >> m) & 1u) && node_of(w[m]) != x[m];
+            if (walk && node_of(w[m]) >= n) {
+                bad = true;
+                return;
+            }
+            wp[m] = walk ? nodes[node_of(w[m])] : w[m];
+            done &= !walk;
+        }
+        if (done) return;
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            if (((live >> m) & 1u) && node_of(w[m]) != x[m] && !n_step(nodes, n, x[m], w[m], wp[m], bad)) return;
+    }
+    bad = true;
+}
+
 // Join the clusters of nodes a and b (a, b < n; words wa, wb already loaded).
 __device__ void n_unite(gptr<uint64_t> nodes, uint32_t n, uint32_t a, uint32_t b, uint64_t wa, uint64_t wb, bool& bad)
 {
@@ -563,7 +591,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     // The first lane to reach a root claims it as a node of the tile's edge
     // forest: it takes the next slot (in no particular order: a node's word
     // carries its key), writes the node's word (a root of its own, keyed by its
-    // site index) and tags the root's LDS entry ROOT | slot, which the labels
+    // site index) and tags the root's LDS entry ROOT16 | slot, which the labels
     // and the edge record copy.  Walks stop at tagged entries.
     // a site index fits 32 bits (N <= 2^32) and y, L fit 24 bits
     auto global_index = [&](uint32_t la) { return __umul24(y0 + la / TX, L) + x0 + la % TX; };
@@ -607,17 +635,17 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     __syncthreads();
     if (tid == 0) rec[6] = tot[2];   // nodes of the tile
 
-    // Labels out, per site: the tile-local index of its union-find grandparent
-    // (a smaller site of its tile-local cluster; the flip follows these
-    // pointers inside the tile), or, for a tile-local root, ROOT | its slot
-    // (NOSLOT if its cluster touches no tile edge).  A grandparent that is a
+    // Tile labels out (16 bits), per site: the tile-local index of its
+    // union-find grandparent (a smaller site of its tile-local cluster; the
+    // flip follows these pointers inside the tile), or, for a tile-local root,
+    // ROOT16 | its slot (NOSLOT if its cluster touches no tile edge).  A grandparent that is a
     // node is not copied (its entry carries a slot, not an index): the parent
     // is.  (The grandparent read is masked into the tile: a tagged entry's
     // slot, or an unused column's entry, reads some entry that is not used.)
     // Entries of columns outside the tile are never stored (full-width tiles,
     // the common case, need no mask at all).
     auto label_of = [&](uint32_t li, uint32_t p, uint32_t gp) {
-        return (p & ROOT16) ? (ROOT | (p & ~ROOT16)) : (p == li) ? (ROOT | NOSLOT) : (gp & ROOT16) ? p : gp;
+        return (p & ROOT16) ? p : (p == li) ? (ROOT16 | NOSLOT) : (gp & ROOT16) ? p : gp;
     };
     auto labels_out = [&](auto full) {
         constexpr bool FULL = decltype(full)::value;
@@ -625,8 +653,8 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         for (uint32_t r = r0; r < r1; ++r) {
             const uint32_t li = r * TX + x, p = P[li];
             const uint32_t out = label_of(li, p, P[p & (TY * TX - 1u)]);
-            const gptr<uint32_t> lrow = glb(d.lab) + (size_t)(y0 + r) * L + x0;
-            if (vs) lrow[x] = out;
+            const gptr<uint16_t> lrow = glb(d.tlab) + (size_t)(y0 + r) * L + x0;
+            if (vs) lrow[x] = (uint16_t)out;
         }
     };
     if (w == TX && r1 - r0 == RPW) {
@@ -638,10 +666,10 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         for (uint32_t k = 0; k < RPW; ++k) p[k] = P[(r0 + k) * TX + x];   // (16-bit entries)
 #pragma unroll
         for (uint32_t k = 0; k < RPW; ++k) gp[k] = P[p[k] & (TY * TX - 1u)];
-        const gptr<char> strip = (gptr<char>)(glb(d.lab) + (size_t)(y0 + r0) * L + x0);
+        const gptr<char> strip = (gptr<char>)(glb(d.tlab) + (size_t)(y0 + r0) * L + x0);
 #pragma unroll
         for (uint32_t k = 0; k < RPW; ++k)
-            *(gptr<uint32_t>)(strip + (k * L + x) * 4u) = label_of((r0 + k) * TX + x, p[k], gp[k]);
+            *(gptr<uint16_t>)(strip + (k * L + x) * 2u) = (uint16_t)label_of((r0 + k) * TX + x, p[k], gp[k]);
     } else if (w == TX) {
         labels_out(std::true_type{});
     } else {
@@ -701,16 +729,22 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
     uint32_t pa = INVALID, pb = INVALID;
     for (uint32_t j = 0; j < TY; j += 64) {
         const uint32_t r = j + lane, x = lane;
-        const bool right = r < g.h && ((rec[r >> 5] >> (r & 31u)) & 1u);
-        const bool below = j == 0 && x < g.w && ((rec[4 + (x >> 5)] >> (x & 31u)) & 1u);
+        // the crossing bits and the slots at both ends of every edge site are
+        // loaded together (all inside the records; slots of sites without a
+        // crossing bond are not used)
+        const uint32_t wr = rec[r >> 5], wb = rec[4 + (x >> 5)];
+        const uint32_t sa1 = sl[r], sb1 = slR[TY + r];
+        const uint32_t sa2 = sl[2 * TY + x], sb2 = slB[2 * TY + TX + x];
+        const bool right = r < g.h && ((wr >> (r & 31u)) & 1u);
+        const bool below = j == 0 && x < g.w && ((wb >> (x & 31u)) & 1u);
         uint32_t a1 = INVALID, b1 = INVALID, a2 = INVALID, b2 = INVALID;
         if (right) {
-            a1 = tile * NS + sl[r];
-            b1 = t_right * NS + slR[TY + r];
+            a1 = tile * NS + sa1;
+            b1 = t_right * NS + sb1;
         }
         if (below) {
-            a2 = tile * NS + sl[2 * TY + x];
-            b2 = t_below * NS + slB[2 * TY + TX + x];
+            a2 = tile * NS + sa2;
+            b2 = t_below * NS + sb2;
         }
         uint32_t ua = __shfl_up(a1, 1), ub = __shfl_up(b1, 1);
         uint32_t va = __shfl_up(a2, 1), vb = __shfl_up(b2, 1);
@@ -725,10 +759,23 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
         const bool u1 = right && !(ua == a1 && ub == b1) && a1 < n && b1 < n;
         const bool u2 = below && !(va == a2 && vb == b2) && a2 < n && b2 < n;
         bad |= (right && !(a1 < n && b1 < n)) || (below && !(a2 < n && b2 < n));
-        const uint64_t wa1 = u1 ? nodes[a1] : 0ull, wb1 = u1 ? nodes[b1] : 0ull;
-        const uint64_t wa2 = u2 ? nodes[a2] : 0ull, wb2 = u2 ? nodes[b2] : 0ull;
-        if (u1) n_unite(nodes, n, a1, b1, wa1, wb1, bad);
-        if (u2) n_unite(nodes, n, a2, b2, wa2, wb2, bad);
+        // both unions' four walks in step, then both hooks; a hook on a root
+        // that was hooked meanwhile carries on as a plain union
+        uint32_t xs[4] = {a1, b1, a2, b2};
+        uint64_t ws[4] = {u1 ? nodes[a1] : 0ull, u1 ? nodes[b1] : 0ull, u2 ? nodes[a2] : 0ull, u2 ? nodes[b2] : 0ull};
+        n_find_m<4>(nodes, n, xs, ws, (u1 ? 3u : 0u) | (u2 ? 12u : 0u), bad);
+        const bool h1 = u1 && !bad && ws[0] != ws[1], h2 = u2 && !bad && ws[2] != ws[3];
+        const uint64_t hi1 = max(ws[0], ws[1]), lo1 = min(ws[0], ws[1]);
+        const uint64_t hi2 = max(ws[2], ws[3]), lo2 = min(ws[2], ws[3]);
+        const uint64_t old1 = h1 ? min_coherent64(nodes + node_of(hi1), lo1) : hi1;
+        const uint64_t old2 = h2 ? min_coherent64(nodes + node_of(hi2), lo2) : hi2;
+        auto again = [&](uint64_t old, uint64_t lo) {
+            const uint32_t p = node_of(old);
+            if (p >= n) bad = true;
+            else n_unite(nodes, n, p, node_of(lo), nodes[p], lo, bad);
+        };
+        if (old1 != hi1) again(old1, lo1);
+        if (old2 != hi2) again(old2, lo2);
     }
     if (bad) flag_error(d.err);
 }
@@ -780,7 +827,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     // arrays), which keeps 64-bit address arithmetic out of the vector units.
     const uint32_t site0 = wave * L + col;         // this lane's first site, from the tile origin
     const uint32_t wave_step = NW * L;             // sites between a wave's consecutive rows
-    const gptr<const char> lab_tile = (gptr<const char>)(glb(d.lab) + (size_t)y0 * L + x0);
+    const gptr<const char> lab_tile = (gptr<const char>)(glb(d.tlab) + (size_t)y0 * L + x0);
     const gptr<char> s_tile = (gptr<char>)(glb(d.s) + (size_t)y0 * L + x0);
     const uint32_t n_used = min(glb(d.edges)[(size_t)tile * edge_words(TY) + 6], NS);
     // XY: the sweep's direction (wave-uniform)
@@ -794,8 +841,8 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
             const uint32_t r = wave + NW * j;
-            const uint32_t byte_off = (site0 + j * wave_step) * 4u;
-            v[j] = (vcol && (FULL || r < h)) ? *(gptr<const uint32_t>)(lab_tile + byte_off) : 0u;
+            const uint32_t byte_off = (site0 + j * wave_step) * 2u;
+            v[j] = (vcol && (FULL || r < h)) ? *(gptr<const uint16_t>)(lab_tile + byte_off) : 0u;
         }
         const uint32_t nj = lane * NW + wave;   // this lane's node
         const bool is_node = nj < n_used;
@@ -810,12 +857,12 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
             if (!FULL && r >= h) continue;
             const uint32_t li = li0 + j * NW * TX;
             const uint32_t vv = v[j];
-            const bool root = (vv & ROOT) != 0u;
-            const uint32_t slot = vv & 0xFFFFu;
+            const bool root = (vv & ROOT16) != 0u;
+            const uint32_t slot = vv & ~ROOT16;
             // a pointer must go to a smaller site, a slot to a node of the tile
             bad |= vcol && (root ? (slot != NOSLOT && slot >= n_used) : vv >= li);
             const uint64_t m = ballot(vcol && root && slot == NOSLOT);
-            if (vcol) E[li] = root ? (ROOT16 | (slot & 0x7FFFu)) : vv;
+            if (vcol) E[li] = vv;
             // roots inside the tile append to the list, the other lanes write their scratch slot
             const uint32_t at_list = nterm + lanes_below(m), at_scratch = PER * TX + 64 + lane;
             my_list[lane_in(m) ? at_list : at_scratch] = (uint16_t)li;
@@ -969,13 +1016,12 @@ __global__ __launch_bounds__(threads_of<TY>()) void k_csize(const LatDesc* descs
     const uint32_t t = *glb(d.counter) + k;
     const uint32_t tid = threadIdx.x;
     const uint32_t NS = nslot(TY), n_nodes = d.ntiles * NS, node0 = tile * NS;
-    const gptr<uint32_t> lab = glb(d.lab);
+    const gptr<const uint16_t> lab = glb(d.tlab);
     bool bad = false;
     if (tid < 3) sums[tid] = 0;
     for (uint32_t li = tid; li < TY * TX; li += NT) {
         const uint32_t r = li / TX, c = li % TX;
-        const uint32_t v = (r < g.h && c < g.w) ? lab[(size_t)(g.y0 + r) * d.L + g.x0 + c] : (ROOT | NOSLOT);
-        E[li] = (v & ROOT) ? (ROOT16 | (v & 0x7FFFu)) : v;
+        E[li] = (r < g.h && c < g.w) ? lab[(size_t)(g.y0 + r) * d.L + g.x0 + c] : (ROOT16 | NOSLOT);
         C[li] = 0;
     }
     __syncthreads();
@@ -1104,44 +1150,49 @@ __global__ __launch_bounds__(256) void k_init(const LatDesc* descs, uint32_t lat
     }
 }
 
-// Labels of the last sweep resolved, in place, to the smallest site index of
-// each cluster: one workgroup per tile walks its sites' pointers in LDS to
-// their tile-local roots and those, if they are nodes, to the edge forest's
-// roots.  The sweep does not read the labels again before it writes them anew.
+// The last sweep's labels of rows [ya, yb) resolved to the smallest site index
+// of each cluster, written from the base of the label region (row ya first):
+// one workgroup per tile walks its sites' pointers in LDS to their tile-local
+// roots and those, if they are nodes, to the edge forest's roots.  The tile
+// labels (upper half of the region) are only read, so that (yb - ya) L <= N/2
+// keeps the output clear of them.
 template <int TY>
-__global__ __launch_bounds__(threads_of<TY>()) void k_resolve(const LatDesc* descs, uint32_t lat)
+__global__ __launch_bounds__(threads_of<TY>()) void k_resolve(const LatDesc* descs, uint32_t lat, uint32_t ya,
+                                                              uint32_t yb)
 {
     constexpr uint32_t NT = threads_of<TY>();
-    __shared__ uint32_t E[TY * TX];
+    __shared__ uint16_t E[TY * TX];
     const LatDesc d = descs[lat];
     const uint32_t tile = blockIdx.x;
     if (tile >= d.ntiles) return;
     const TileGeom g = tile_geom(d, tile, TY);
+    if (g.y0 >= yb || g.y0 + g.h <= ya) return;
     const uint32_t NS = nslot(TY), n_nodes = d.ntiles * NS, node0 = tile * NS;
-    const gptr<uint32_t> lab = glb(d.lab);
+    const gptr<const uint16_t> lab = glb(d.tlab);
+    const gptr<uint32_t> out = glb(d.lab);
     bool bad = false;
     for (uint32_t li = threadIdx.x; li < TY * TX; li += NT) {
         const uint32_t r = li / TX, c = li % TX;
-        E[li] = (r < g.h && c < g.w) ? lab[(size_t)(g.y0 + r) * d.L + g.x0 + c] : (ROOT | NOSLOT);
+        E[li] = (r < g.h && c < g.w) ? lab[(size_t)(g.y0 + r) * d.L + g.x0 + c] : (ROOT16 | NOSLOT);
     }
     __syncthreads();
     for (uint32_t li = threadIdx.x; li < TY * TX; li += NT) {
-        const uint32_t r = li / TX, c = li % TX;
-        if (r >= g.h || c >= g.w) continue;
+        const uint32_t r = li / TX, c = li % TX, y = g.y0 + r;
+        if (r >= g.h || c >= g.w || y < ya || y >= yb) continue;
         uint32_t cur = li, v = E[cur];
-        while (!(v & ROOT) && v < cur) {
+        while (!(v & ROOT16) && v < cur) {
             cur = v;
             v = E[cur];
         }
         uint32_t root = INVALID;
-        if (!(v & ROOT)) {
+        if (!(v & ROOT16)) {
             bad = true;
-        } else if ((v & 0xFFFFu) == NOSLOT) {
+        } else if ((v & ~ROOT16) == NOSLOT) {
             root = (g.y0 + cur / TX) * d.L + g.x0 + cur % TX;
         } else {
-            root = key_of(n_root(glb(d.nodes), n_nodes, node0 + (v & 0xFFFFu), bad));
+            root = key_of(n_root(glb(d.nodes), n_nodes, node0 + (v & ~ROOT16), bad));
         }
-        lab[(size_t)(g.y0 + r) * d.L + g.x0 + c] = root;
+        out[(size_t)(y - ya) * d.L + g.x0 + c] = root;
     }
     if (bad) flag_error(d.err);
 }
@@ -1319,12 +1370,15 @@ hipError_t launch_init(const LatDesc* descs, uint32_t lat, size_t N, uint32_t ra
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, uint32_t ntiles, uint32_t ty, hipStream_t s)
+hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, uint32_t ntiles, uint32_t ty, uint32_t ya, uint32_t yb,
+                          hipStream_t s)
 {
     switch (ty) {
-    case 32: hipLaunchKernelGGL(k_resolve<32>, dim3(ntiles), dim3(threads_of<32>()), 0, s, descs, lat); break;
-    case 64: hipLaunchKernelGGL(k_resolve<64>, dim3(ntiles), dim3(threads_of<64>()), 0, s, descs, lat); break;
-    case 128: hipLaunchKernelGGL(k_resolve<128>, dim3(ntiles), dim3(threads_of<128>()), 0, s, descs, lat); break;
+    case 32: hipLaunchKernelGGL(k_resolve<32>, dim3(ntiles), dim3(threads_of<32>()), 0, s, descs, lat, ya, yb); break;
+    case 64: hipLaunchKernelGGL(k_resolve<64>, dim3(ntiles), dim3(threads_of<64>()), 0, s, descs, lat, ya, yb); break;
+    case 128:
+        hipLaunchKernelGGL(k_resolve<128>, dim3(ntiles), dim3(threads_of<128>()), 0, s, descs, lat, ya, yb);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

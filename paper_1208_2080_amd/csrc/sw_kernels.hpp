@@ -48,8 +48,10 @@ hipError_t launch_xy_init(const LatDesc* descs, size_t N, uint32_t random_start,
 // set past the last sweep).
 hipError_t launch_whole(const LatDesc* descs, const uint32_t* list, uint32_t count, uint32_t lmax, uint32_t k0,
                         uint32_t n_uniform, const uint32_t* n_each, uint32_t flags, uint32_t ty, hipStream_t s);
-// Labels of the last sweep resolved in place to smallest site indices.
-hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, uint32_t ntiles, uint32_t ty, hipStream_t s);
+// Labels of rows [ya, yb) of the last sweep resolved to smallest site
+// indices, written from the base of the label region ((yb - ya) L <= N / 2).
+hipError_t launch_resolve(const LatDesc* descs, uint32_t lat, uint32_t ntiles, uint32_t ty, uint32_t ya, uint32_t yb,
+                          hipStream_t s);
 // Sum the NCOPY partial copies of n ring records of `words` words (copies
 // `stride` words apart), from slot slot0 on (wrapping at `slots`), into
 // out[n][words].

@@ -5,13 +5,19 @@
 // column c of its tile):
 //   spins   uint8  [N]        Potts states; for an XY lattice uint32 [N]
 //                             angles instead (unit: 2^-32 of a full turn)
-//   labels  uint32 [N]        after a sweep, per site: the tile-local index of a
-//                             smaller site of its tile-local cluster (its
+//   labels  4N bytes:
+//     tile labels  uint16 [N] at byte offset 2N, written by the labelling and
+//                             read by the flip: per site, the tile-local index
+//                             of a smaller site of its tile-local cluster (its
 //                             union-find grandparent in the tile), or, for the
 //                             cluster's smallest site (its tile-local root),
-//                             ROOT | slot, slot the root's node in the tile's
+//                             ROOT16 | slot, slot the root's node in the tile's
 //                             edge forest, NOSLOT if the cluster touches no
 //                             tile edge
+//     resolved     uint32 from byte 0: smallest site indices of the clusters,
+//                             for label reads (at most N/2 sites at a time, so
+//                             the tile labels stay intact); a lattice swept
+//                             whole in LDS writes all N of them here instead
 //   bonds   uint64 [tiles][2][TY]  tile-major bond words: tile t, plane p (0: +x,
 //                             1: +y), row r; bit x = bond of site (x0 + x, y0 + r)
 //   edges   uint32 [tiles][edge_words(TY)]  per-tile boundary record (below)
@@ -38,10 +44,8 @@ namespace swmi {
 
 constexpr uint32_t TX = 64;           // tile width: one wave, one column per lane
 constexpr uint32_t NCOPY = 64;        // partial copies of each ring record
-constexpr uint32_t TERM = 0x80000000u;     // flip: entry resolved to a state
-constexpr uint32_t ROOT = 0x80000000u;     // label of a tile-local root
 constexpr uint32_t NOSLOT = 0x7FFFu;       // root of a cluster inside its tile
-constexpr uint32_t ROOT16 = 0x8000u;       // tile-local root's tag in 16-bit entries
+constexpr uint32_t ROOT16 = 0x8000u;       // tile-local root's tag in 16-bit entries and tile labels
 constexpr uint32_t INVALID = 0xFFFFFFFFu;
 constexpr uint32_t WHOLE_LMAX = 128;       // largest L swept whole in one workgroup's LDS
 
@@ -91,7 +95,8 @@ struct DevState {
 
 struct LatDesc {
     uint8_t* s;
-    uint32_t* lab;
+    uint32_t* lab;         // resolved labels (base of the label region)
+    uint16_t* tlab;        // tile labels (upper half of the label region)
     uint64_t* bonds;
     uint32_t* edges;
     uint64_t* nodes;       // edge forest, nslot(TY) words per tile

@@ -190,14 +190,15 @@ def test_corrupted_label_forest_is_reported_not_walked():
     # the tile kernels' label format (a small lattice is otherwise swept whole)
     lat = binding.Lattice(L, 2, wl.critical_coupling(2), seed=3, obs_capacity=4, tile_rows=64)
     lat.sweep(1)
-    # the labels follow the state (256 B), the descriptor (one 256-byte block)
-    # and the spins (L*L bytes, 256-aligned) in the workspace
-    off = 256 + 256 + ((L * L + 255) // 256) * 256
-    words = lat.ws[off:off + 4 * L * L].view(torch.int32)
-    raw = words.cpu().numpy().view(np.uint32).reshape(L, L)
-    local = (np.arange(L)[:, None] * 64 + np.arange(L)[None, :]).astype(np.uint32)
+    # the label region follows the state (256 B), the descriptor (one 256-byte
+    # block) and the spins (L*L bytes, 256-aligned) in the workspace; its upper
+    # half holds the 16-bit tile labels
+    off = 256 + 256 + ((L * L + 255) // 256) * 256 + 2 * L * L
+    words = lat.ws[off:off + 2 * L * L].view(torch.int16)
+    raw = words.cpu().numpy().view(np.uint16).reshape(L, L)
+    local = (np.arange(L)[:, None] * 64 + np.arange(L)[None, :]).astype(np.uint16)
     # as stored by the sweep: a tile-local root's tag, or a smaller site of the tile
-    assert np.all((raw & np.uint32(0x80000000)) | (raw < local))
+    assert np.all((raw & np.uint16(0x8000)) | (raw < local))
     words[5] = 3 * 64 + 2                    # site 5 now points at a larger site of its tile
     torch.cuda.synchronize()
     with pytest.raises(binding.SwError) as e:
