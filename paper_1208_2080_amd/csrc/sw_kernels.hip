@@ -138,24 +138,6 @@ __device__ __forceinline__ bool n_step(gptr<uint64_t> nodes, uint32_t n, uint32_
     return true;
 }
 
-// Roots of nodes a and b (words wa, wb already loaded), both chains walked
-// together so that their loads overlap.  On return a, b are the root nodes
-// and wa, wb their words.
-__device__ void n_find2(gptr<uint64_t> nodes, uint32_t n, uint32_t& a, uint64_t& wa, uint32_t& b, uint64_t& wb,
-                        bool& bad)
-{
-    for (uint32_t it = 0; it < UNITE_CAP; ++it) {
-        const bool ra = node_of(wa) == a, rb = node_of(wb) == b;
-        if (ra && rb) return;
-        if (node_of(wa) >= n || node_of(wb) >= n) break;
-        const uint64_t wpa = ra ? wa : nodes[node_of(wa)];
-        const uint64_t wpb = rb ? wb : nodes[node_of(wb)];
-        if (!ra && !n_step(nodes, n, a, wa, wpa, bad)) return;
-        if (!rb && !n_step(nodes, n, b, wb, wpb, bad)) return;
-    }
-    bad = true;
-}
-
 // Roots of M nodes x[m] (words w[m] already loaded; only the chains whose bit
 // is set in `live` are walked), one level of every unfinished chain per step so
 // that the loads of all chains overlap.
@@ -184,21 +166,38 @@ __device__ void n_find_m(gptr<uint64_t> nodes, uint32_t n, uint32_t (&x)[M], uin
     bad = true;
 }
 
-// Join the clusters of nodes a and b (a, b < n; words wa, wb already loaded).
-__device__ void n_unite(gptr<uint64_t> nodes, uint32_t n, uint32_t a, uint32_t b, uint64_t wa, uint64_t wb, bool& bad)
+// Every word in the forest, (key << 32) | p, is also the word node p holds
+// while it is a root (a node's key is its own).  So a hook can name two roots
+// by their words alone: hook(a, b) hangs the node of the larger word under the
+// smaller with one atomicMin.  If that node was no longer a root, the atomic
+// returns its current word, whose node is the parent it had meanwhile gained
+// (and a smaller word stored by the atomic dropped that link), so the hook goes
+// on with that word and the smaller one: no reload and no new walk, one round
+// trip per attempt.  The larger word falls at every attempt, so the loop ends.
+// Two hooks of one lane run in step so that their atomics overlap.
+__device__ void n_hook2(gptr<uint64_t> nodes, uint32_t n, uint64_t (&a)[2], uint64_t (&b)[2], bool& bad)
 {
     for (uint32_t it = 0; it < UNITE_CAP; ++it) {
-        n_find2(nodes, n, a, wa, b, wb, bad);
-        if (wa == wb || bad) return;
-        const uint64_t hi = max(wa, wb), lo = min(wa, wb);
-        const uint64_t old = min_coherent64(nodes + node_of(hi), lo);
-        if (old == hi) return;
-        // hi was hooked meanwhile: join its new parent with lo instead
-        a = node_of(old);
-        b = node_of(lo);
-        if (a >= n) break;
-        wa = nodes[a];
-        wb = lo;
+        bool done = true;
+        uint64_t old[2], hi[2], lo[2];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            hi[m] = max(a[m], b[m]);
+            lo[m] = min(a[m], b[m]);
+            const bool act = hi[m] != lo[m];
+            if (act && node_of(hi[m]) >= n) {
+                bad = true;
+                return;
+            }
+            old[m] = act ? min_coherent64(nodes + node_of(hi[m]), lo[m]) : hi[m];
+        }
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            a[m] = old[m] == hi[m] ? lo[m] : old[m];
+            b[m] = lo[m];
+            done &= old[m] == hi[m];
+        }
+        if (done) return;
     }
     bad = true;
 }
@@ -759,23 +758,13 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
         const bool u1 = right && !(ua == a1 && ub == b1) && a1 < n && b1 < n;
         const bool u2 = below && !(va == a2 && vb == b2) && a2 < n && b2 < n;
         bad |= (right && !(a1 < n && b1 < n)) || (below && !(a2 < n && b2 < n));
-        // both unions' four walks in step, then both hooks; a hook on a root
-        // that was hooked meanwhile carries on as a plain union
+        // both unions' four walks in step, then both hooks
         uint32_t xs[4] = {a1, b1, a2, b2};
         uint64_t ws[4] = {u1 ? nodes[a1] : 0ull, u1 ? nodes[b1] : 0ull, u2 ? nodes[a2] : 0ull, u2 ? nodes[b2] : 0ull};
         n_find_m<4>(nodes, n, xs, ws, (u1 ? 3u : 0u) | (u2 ? 12u : 0u), bad);
-        const bool h1 = u1 && !bad && ws[0] != ws[1], h2 = u2 && !bad && ws[2] != ws[3];
-        const uint64_t hi1 = max(ws[0], ws[1]), lo1 = min(ws[0], ws[1]);
-        const uint64_t hi2 = max(ws[2], ws[3]), lo2 = min(ws[2], ws[3]);
-        const uint64_t old1 = h1 ? min_coherent64(nodes + node_of(hi1), lo1) : hi1;
-        const uint64_t old2 = h2 ? min_coherent64(nodes + node_of(hi2), lo2) : hi2;
-        auto again = [&](uint64_t old, uint64_t lo) {
-            const uint32_t p = node_of(old);
-            if (p >= n) bad = true;
-            else n_unite(nodes, n, p, node_of(lo), nodes[p], lo, bad);
-        };
-        if (old1 != hi1) again(old1, lo1);
-        if (old2 != hi2) again(old2, lo2);
+        if (bad) break;
+        uint64_t ha[2] = {ws[0], ws[2]}, hb[2] = {ws[1], ws[3]};
+        n_hook2(nodes, n, ha, hb, bad);
     }
     if (bad) flag_error(d.err);
 }
@@ -814,7 +803,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     if (!pick(descs, map, blockIdx.x, true, d, tile, lat)) return;
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t t = *glb(d.counter) + k;
-    const uint32_t tid = threadIdx.x, wave = tid >> 6, lane = tid & 63u;
+    const uint32_t tid = threadIdx.x, wave = wave_id(), lane = tid & 63u;
     const uint32_t L = d.L, w = g.w, h = g.h, x0 = g.x0, y0 = g.y0;
     const uint32_t col = lane;
     uint16_t* my_list = list[wave];
@@ -824,7 +813,8 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
 
     // The tile's entries are addressed from a wave-uniform base with 32-bit
     // per-lane byte offsets (a tile spans fewer than 2^32 / 4 sites of the
-    // arrays), which keeps 64-bit address arithmetic out of the vector units.
+    // arrays), which keeps 64-bit address arithmetic out of the vector units;
+    // the wave index is scalar, so the rows' offsets are too.
     const uint32_t site0 = wave * L + col;         // this lane's first site, from the tile origin
     const uint32_t wave_step = NW * L;             // sites between a wave's consecutive rows
     const gptr<const char> lab_tile = (gptr<const char>)(glb(d.tlab) + (size_t)y0 * L + x0);
@@ -848,33 +838,40 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         const bool is_node = nj < n_used;
         const uint64_t nw = is_node ? nodes[node0 + nj] : 0ull;
 
-        // row j of this wave: tile index li0 + j NW TX
+        // row j of this wave: tile index li0 + j NW TX.  The labels go to E; bit
+        // j of `roots` marks a root (tagged ROOT16: a node, or a cluster inside
+        // the tile).  A pointer to a larger site is found by the walk below.
         const uint32_t li0 = wave * TX + col;
-        uint32_t nterm = 0;   // wave-uniform
+        uint32_t roots = 0;
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
             const uint32_t r = wave + NW * j;
             if (!FULL && r >= h) continue;
+            if (vcol) E[li0 + j * NW * TX] = (uint16_t)v[j];
+            roots |= (v[j] >> 15) << j;   // 0 outside the tile
+        }
+        // The roots, one per lane and step (steps while any lane has one left):
+        // a cluster inside the tile joins this wave's list, a node's slot must
+        // name a node of the tile.
+        uint32_t nterm = 0;   // wave-uniform
+        while (ballot(roots != 0)) {
+            const bool has = roots != 0;
+            const uint32_t j = __builtin_ctz(roots | (1u << PER));
+            roots &= roots - 1u;
             const uint32_t li = li0 + j * NW * TX;
-            const uint32_t vv = v[j];
-            const bool root = (vv & ROOT16) != 0u;
-            const uint32_t slot = vv & ~ROOT16;
-            // a pointer must go to a smaller site, a slot to a node of the tile
-            bad |= vcol && (root ? (slot != NOSLOT && slot >= n_used) : vv >= li);
-            const uint64_t m = ballot(vcol && root && slot == NOSLOT);
-            if (vcol) E[li] = vv;
-            // roots inside the tile append to the list, the other lanes write their scratch slot
-            const uint32_t at_list = nterm + lanes_below(m), at_scratch = PER * TX + 64 + lane;
-            my_list[lane_in(m) ? at_list : at_scratch] = (uint16_t)li;
-            nterm = __builtin_amdgcn_readfirstlane(nterm + popc64(m));
+            const uint32_t vv = has ? (uint32_t)E[li & (TY * TX - 1u)] : 0u;
+            const bool inside = vv == (ROOT16 | NOSLOT);
+            bad |= has && !inside && (vv & ~ROOT16) >= n_used;
+            const uint64_t m = ballot(has && inside);
+            if (has && inside) my_list[nterm + lanes_below(m)] = (uint16_t)li;
+            nterm += popc64(m);
         }
         // this wave's nodes find their roots' keys and join the list
         if (is_node) NK[nj] = key_of(n_find_from(nodes, n_nodes, node0 + nj, nw, bad));
         {
             const uint64_t m = ballot(is_node);
-            const uint32_t at_list = nterm + lanes_below(m), at_scratch = PER * TX + 64 + lane;
-            my_list[lane_in(m) ? at_list : at_scratch] = (uint16_t)(NODE_ENTRY | nj);
-            nterm = __builtin_amdgcn_readfirstlane(nterm + popc64(m));
+            if (is_node) my_list[nterm + lanes_below(m)] = (uint16_t)(NODE_ENTRY | nj);
+            nterm += popc64(m);
         }
 
         // the states, 64 list entries at a time; lanes past the end work on a
@@ -895,9 +892,11 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         // Every site follows in-tile pointers (each to a smaller tile index, so
         // the walk ends) to a root: resolved inside the tile, or a node whose
         // state is in the table; the new spins are stored at the end.
+        // (A root's entry, ROOT16 and up, is larger than every tile index, so
+        // `x < cur` alone continues the walk.)
         auto walk = [&](uint32_t j) -> uint32_t {
             uint32_t cur = li0 + j * NW * TX, x = E[cur];
-            while (!(x & ROOT16) && x < cur) {
+            while (x < cur) {
                 cur = x;
                 x = E[cur];
             }
