@@ -304,11 +304,10 @@ __device__ __forceinline__ void drain(UnionQueue& uq, uint16_t* P, uint32_t lane
 
 // Queue the unions (a, b) of the lanes in `mask` where a != b (at most 64; the
 // caller keeps at least 64 slots free).  The other lanes store to a scratch
-// word instead of branching around the store.
+// word instead of branching around the store (no branch on the scalar unit).
 __device__ __forceinline__ void enqueue(UnionQueue& uq, uint64_t mask, uint32_t a, uint32_t b)
 {
     const uint64_t m = ballot(a != b) & mask;
-    if (!m) return;
     lds_st(lane_in(m) ? &uq.q[uq.n + lanes_below(m)] : uq.trash, a | (b << 16));
     uq.n = __builtin_amdgcn_readfirstlane(uq.n + popc64(m));
 }
@@ -337,7 +336,7 @@ __device__ __forceinline__ uint32_t row_labels(uint16_t* P, uint32_t* rl, UnionQ
     const uint32_t lab = lds_ld(&rl[ri]);
     lds_st(&P[fresh], lab);   // columns outside the tile write entries no one reads
     // bonds x-1 and x from the same run above into the same run here add nothing
-    const uint64_t R = V & (V << 1) & C & (hprev << 1);
+    const uint64_t R = (V & C) & ((V & hprev) << 1);
     enqueue(uq, V & ~R, lp, lab);
     return lab;
 }
@@ -413,8 +412,9 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     const bool q2 = d.q == 2;
     uint32_t* rl = RL[wave];
     UnionQueue uq{UQ[wave], &UQT[wave], 0u};
-    // measurement: equal-spin pairs counted per wave (scalar), q = 2 spins
-    // summed per lane (column), active bonds counted from the bond words
+    // measurement: equal-spin pairs and q = 2 spins counted per lane (column;
+    // vector adds keep the work off the scalar unit), active bonds counted from
+    // the bond words
     uint32_t n_eq = 0, ones = 0;
     // q <= 16: each lane counts its sites in states 1..q-1 in the bytes of two
     // 64-bit words (at most 16 rows per lane, so no byte overflows)
@@ -426,13 +426,22 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     bool bad = false;   // this lane met a corrupted forest
     uint64_t hprev = 0, vprev = 0;
 
-    // The row loop, compiled twice: the q = 9..16 counters (two words per lane)
-    // stay out of the common instantiation, whose code they would otherwise
-    // perturb.
-    auto strip_rows = [&](auto wide) {
+    // The row loop, compiled three times: the q = 9..16 counters (two words per
+    // lane) stay out of the common instantiations, whose code they would
+    // otherwise perturb; FAST is a full strip of a full-width tile of a lattice
+    // of even L, q <= 8 and K > 0: no lane or row masks, always two rows, one
+    // Philox path, the measurement counted without branches (used only when
+    // measuring) and the bond words gathered into lanes, one row per lane, and
+    // stored once per strip.  That keeps the scalar unit's share of the loop
+    // small (it is the busier of the two issue units here).
+    auto strip_rows = [&](auto wide, auto fast) {
         constexpr bool WIDE = decltype(wide)::value;
+        constexpr bool FAST = decltype(fast)::value;
+        const uint64_t vm = FAST ? ~0ull : validm, bm = FAST ? ~0ull : bondm;
+        uint32_t bxl = 0, bxh = 0, byl = 0, byh = 0;   // FAST: lane k holds row r0 + k's bond words
+#pragma unroll 1
         for (uint32_t r = r0; r < r1; r += 2) {
-            const bool two = r + 1 < r1;
+            const bool two = FAST || r + 1 < r1;
             if (uq.n > QCAP - 128) drain(uq, P, lane, bad);
             const uint8_t* row = sp + r * SPW;
             const uint32_t s0 = row[x], s0r = row[x + 1];
@@ -443,7 +452,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
             // a draw for row r+1 past the last row wraps but is never used.
             const uint32_t base0 = (y0 + r) * L + x0;
             uint32_t wx0, wy0, wx1, wy1;
-            if (even_L) {
+            if (FAST || even_L) {
                 const bool odd = x & 1u;
                 const uint32_t pair = ((odd ? base0 + L : base0) + (x & ~1u)) >> 1;
                 const u32x4 q4 = philox4x32_10(pair, 0u, t, 0u, ks);
@@ -463,17 +472,25 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
                 wy1 = (gb & 1u) ? qb.w : qb.y;
             }
             // equal-spin masks and draw masks as wave ballots; a bond needs both
-            const uint64_t EX0 = ballot(s0 == s0r) & validm, EY0 = ballot(s0 == s1) & validm;
-            const uint64_t BX0 = EX0 & ballot(wx0 <= d.thr_m1) & bondm;
-            const uint64_t BY0 = EY0 & ballot(wy0 <= d.thr_m1) & bondm;
+            const uint64_t EX0 = ballot(s0 == s0r) & vm, EY0 = ballot(s0 == s1) & vm;
+            const uint64_t BX0 = EX0 & ballot(wx0 <= d.thr_m1) & bm;
+            const uint64_t BY0 = EY0 & ballot(wy0 <= d.thr_m1) & bm;
             uint64_t EX1 = 0, EY1 = 0, BX1 = 0, BY1 = 0;
             if (two) {
-                EX1 = ballot(s1 == s1r) & validm;
-                EY1 = ballot(s1 == s2) & validm;
-                BX1 = EX1 & ballot(wx1 <= d.thr_m1) & bondm;
-                BY1 = EY1 & ballot(wy1 <= d.thr_m1) & bondm;
+                EX1 = ballot(s1 == s1r) & vm;
+                EY1 = ballot(s1 == s2) & vm;
+                BX1 = EX1 & ballot(wx1 <= d.thr_m1) & bm;
+                BY1 = EY1 & ballot(wy1 <= d.thr_m1) & bm;
             }
-            if (lane == 0) {
+            if constexpr (FAST) {
+                // vector selects only (no scalar work): lane k takes row r0 + k
+                const uint32_t k = r - r0;
+                const bool at0 = lane == k, at1 = lane == k + 1;
+                bxl = at0 ? (uint32_t)BX0 : at1 ? (uint32_t)BX1 : bxl;
+                bxh = at0 ? (uint32_t)(BX0 >> 32) : at1 ? (uint32_t)(BX1 >> 32) : bxh;
+                byl = at0 ? (uint32_t)BY0 : at1 ? (uint32_t)BY1 : byl;
+                byh = at0 ? (uint32_t)(BY0 >> 32) : at1 ? (uint32_t)(BY1 >> 32) : byh;
+            } else if (lane == 0) {
                 rb[r][0] = BX0;
                 rb[r][1] = BY0;
                 if (two) {
@@ -495,8 +512,15 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
                 vprev = BY1;
             }
 
-            if (meas_prev) {
-                n_eq += popc64(EX0) + popc64(EY0) + popc64(EX1) + popc64(EY1);   // EX1, EY1 are 0 without row r+1
+            if (FAST) {
+                n_eq += (uint32_t)lane_in(EX0) + (uint32_t)lane_in(EY0) + (uint32_t)lane_in(EX1) +
+                        (uint32_t)lane_in(EY1);
+                count_state_byte(packed, true, s0);
+                count_state_byte(packed, true, s1);
+            } else if (meas_prev) {
+                // this lane's equal pairs (EX1, EY1 are 0 without row r+1)
+                n_eq += (uint32_t)lane_in(EX0) + (uint32_t)lane_in(EY0) + (uint32_t)lane_in(EX1) +
+                        (uint32_t)lane_in(EY1);
                 if (q2) ones += (s0 & vbyte) + (s1 & (two ? vbyte : 0u));
                 else if (q8) {
                     // (lanes outside the tile add nothing; their bytes may be stale)
@@ -511,6 +535,12 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
                 }
             }
         }
+        if constexpr (FAST) {
+            if (lane < RPW) {
+                rb[r0 + lane][0] = ((uint64_t)bxh << 32) | bxl;
+                rb[r0 + lane][1] = ((uint64_t)byh << 32) | byl;
+            }
+        }
     };
     // the same row labelling over bond words that are already in LDS
     auto preset_rows = [&]() {
@@ -522,18 +552,21 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
             vprev = rb[r][1];
         }
     };
+    const bool fast = w == TX && r1 - r0 == RPW && even_L && d.thr_nz && d.q <= 8;
     if constexpr (PRESET) preset_rows();
-    else if (q16 && !q8) strip_rows(std::true_type{});
-    else strip_rows(std::false_type{});
+    else if (q16 && !q8) strip_rows(std::true_type{}, std::false_type{});
+    else if (fast) strip_rows(std::false_type{}, std::true_type{});
+    else strip_rows(std::false_type{}, std::false_type{});
     seam[wave][lane] = lp;
     if (meas_prev) {
         // every site of the strip owns two bonds
-        if (lane == 0 && r0 < r1) atomicAdd(&tot[0], 2u * w * (r1 - r0) - n_eq);
-        if (q2) {
+        const uint32_t eq = wave_sum_small<6>(n_eq);   // a lane counts at most 2 RPW <= 32 pairs
+        if (lane == 0 && r0 < r1) atomicAdd(&tot[0], 2u * w * (r1 - r0) - eq);
+        if (q2 && !fast) {
             const uint32_t n1 = wave_sum_small<6>(ones);   // a lane counts at most TY / 4 <= 32 rows
             if (lane == 0 && n1) atomicAdd(&hist[1], n1);
         }
-        if (q16) flush_state_bytes(packed, hist, d.q, lane);
+        if (q16 || fast) flush_state_bytes(packed, hist, d.q, lane);   // (fast: q <= 8, one word)
     }
     __syncthreads();
 
@@ -658,17 +691,16 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     };
     if (w == TX && r1 - r0 == RPW) {
         // a full strip: all parent reads first, then all grandparent reads, so
-        // the LDS round trips overlap; the stores go out from the strip's
-        // (wave-uniform) base with 32-bit per-lane offsets
+        // the LDS round trips overlap; each row is stored from its own
+        // wave-uniform (scalar) base, the lane's column as the only vector part
         uint32_t p[RPW], gp[RPW];
 #pragma unroll
         for (uint32_t k = 0; k < RPW; ++k) p[k] = P[(r0 + k) * TX + x];   // (16-bit entries)
 #pragma unroll
         for (uint32_t k = 0; k < RPW; ++k) gp[k] = P[p[k] & (TY * TX - 1u)];
-        const gptr<char> strip = (gptr<char>)(glb(d.tlab) + (size_t)(y0 + r0) * L + x0);
+        gptr<uint16_t> out = glb(d.tlab) + (size_t)(y0 + r0) * L + x0 + x;   // this lane's site, row by row
 #pragma unroll
-        for (uint32_t k = 0; k < RPW; ++k)
-            *(gptr<uint16_t>)(strip + (k * L + x) * 2u) = (uint16_t)label_of((r0 + k) * TX + x, p[k], gp[k]);
+        for (uint32_t k = 0; k < RPW; ++k, out += L) *out = (uint16_t)label_of((r0 + k) * TX + x, p[k], gp[k]);
     } else if (w == TX) {
         labels_out(std::true_type{});
     } else {
@@ -811,10 +843,10 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     const gptr<uint64_t> nodes = glb(d.nodes);
     bool bad = false;
 
-    // The tile's entries are addressed from a wave-uniform base with 32-bit
-    // per-lane byte offsets (a tile spans fewer than 2^32 / 4 sites of the
-    // arrays), which keeps 64-bit address arithmetic out of the vector units;
-    // the wave index is scalar, so the rows' offsets are too.
+    // The tile's entries are addressed from one wave-uniform base with 32-bit
+    // per-lane offsets (a tile spans fewer than 2^32 / 4 sites of the arrays):
+    // one vector add per row, where a scalar base per row would cost the busier
+    // scalar unit two 64-bit adds.  Row j of this wave is row wave + NW j.
     const uint32_t site0 = wave * L + col;         // this lane's first site, from the tile origin
     const uint32_t wave_step = NW * L;             // sites between a wave's consecutive rows
     const gptr<const char> lab_tile = (gptr<const char>)(glb(d.tlab) + (size_t)y0 * L + x0);
@@ -828,11 +860,12 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         constexpr bool FULL = decltype(full)::value;
         const bool vcol = FULL || col < w;
         uint32_t v[PER];
+        gptr<const uint16_t> lab_p = (gptr<const uint16_t>)lab_tile + site0;
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
             const uint32_t r = wave + NW * j;
-            const uint32_t byte_off = (site0 + j * wave_step) * 2u;
-            v[j] = (vcol && (FULL || r < h)) ? *(gptr<const uint16_t>)(lab_tile + byte_off) : 0u;
+            v[j] = (vcol && (FULL || r < h)) ? (uint32_t)*lab_p : 0u;
+            lab_p += wave_step;
         }
         const uint32_t nj = lane * NW + wave;   // this lane's node
         const bool is_node = nj < n_used;
@@ -933,10 +966,12 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
                 const uint32_t r = wave + NW * j;
                 e[j] = (vcol && (FULL || r < h)) ? walk(j) : 0u;
             }
+            gptr<uint8_t> s_p = (gptr<uint8_t>)s_tile + site0;
 #pragma unroll
             for (uint32_t j = 0; j < PER; ++j) {
                 const uint32_t r = wave + NW * j;
-                if (vcol && (FULL || r < h)) *(gptr<uint8_t>)(s_tile + (site0 + j * wave_step)) = (uint8_t)e[j];
+                if (vcol && (FULL || r < h)) *s_p = (uint8_t)e[j];
+                s_p += wave_step;
             }
         }
     };
