@@ -36,20 +36,34 @@ def _run(cmd, verbose: bool):
         print(text, flush=True)
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source for gfx950 and link ``libswmi.so`` next to this file."""
+# The profiling build: the same sources with the kernels' phase clocks on
+# (-DSW_PHASE_CLOCKS), linked apart from the product library.
+PHASE_LIB = os.path.join(HERE, "libswmi_phase.so")
+
+
+def build(verbose: bool = False, lib: str = LIB, defines=()) -> str:
+    """Compile every source for gfx950 and link ``lib`` (by default
+    ``libswmi.so`` next to this file) with the given preprocessor defines."""
+    tag = ".phase" if defines else ""
     objs = []
     for src in SOURCES:
-        obj = os.path.join(CSRC, src + ".o")
-        _run([hipcc()] + HIP_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        obj = os.path.join(CSRC, src + tag + ".o")
+        _run([hipcc()] + HIP_FLAGS + ["-D" + d for d in defines] + ["-c", os.path.join(CSRC, src), "-o", obj],
+             verbose)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     _run([hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs, verbose)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for obj in objs:
         os.remove(obj)
-    return LIB
+    return lib
+
+
+def build_phase_clocks(verbose: bool = False) -> str:
+    """The profiling library with the kernels' phase clocks (``libswmi_phase.so``)."""
+    return build(verbose, PHASE_LIB, ("SW_PHASE_CLOCKS",))
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import sys
+    print(build_phase_clocks(verbose=True) if "--phase-clocks" in sys.argv else build(verbose=True))

@@ -343,6 +343,40 @@ __device__ __forceinline__ uint32_t row_labels(uint16_t* P, uint32_t* rl, UnionQ
 
 }  // namespace
 
+#ifdef SW_PHASE_CLOCKS
+// Phase-clock tables of the profiling build: [kernel][NCOPY][PHASES + 1], the
+// kernels being the bond-and-label kernel (Potts), the merge, the flip
+// (Potts), the labelling of preset bonds and the flip that reflects (XY).
+constexpr uint32_t PHASE_KERNELS = 5;
+static __device__ unsigned long long g_phase_table[PHASE_KERNELS * NCOPY * (PHASES + 1)];
+__device__ __forceinline__ unsigned long long* phase_table(uint32_t kernel)
+{
+    return g_phase_table + (size_t)kernel * NCOPY * (PHASES + 1);
+}
+
+// Profiling builds only (C linkage, so the namespace does not matter): the
+// phase-clock tables summed over their rows into
+// host [PHASE_KERNELS][PHASES + 1] (ticks per phase, then waves), and cleared
+// when `clear` is nonzero.  Synchronises the device.
+extern "C" int sw_phase_clocks(unsigned long long* host, int clear)
+{
+    static unsigned long long t[PHASE_KERNELS * NCOPY * (PHASES + 1)];
+    if (hipDeviceSynchronize() != hipSuccess) return -1;
+    if (hipMemcpyFromSymbol(t, HIP_SYMBOL(g_phase_table), sizeof(t)) != hipSuccess) return -1;
+    for (uint32_t k = 0; k < PHASE_KERNELS; ++k)
+        for (uint32_t i = 0; i <= PHASES; ++i) {
+            unsigned long long sum = 0;
+            for (uint32_t c = 0; c < NCOPY; ++c) sum += t[(k * NCOPY + c) * (PHASES + 1) + i];
+            host[k * (PHASES + 1) + i] = sum;
+        }
+    if (clear) {
+        for (auto& v : t) v = 0;
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_phase_table), t, sizeof(t)) != hipSuccess) return -1;
+    }
+    return 0;
+}
+#endif
+
 // ---------------------------------------------------------------------------
 // Bonds + tile-local labels (+ measurement of the incoming configuration).
 //
@@ -382,6 +416,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     LatDesc d;
     uint32_t tile, lat;
     if (!pick(descs, map, blockIdx.x, true, d, tile, lat)) return;
+    SW_PHASE_START(pc);
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t t = *glb(d.counter) + k;
     const bool meas = !PRESET && d.cap != 0;
@@ -401,6 +436,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         stage_spins<TY>(sp, d, g, tid);
     }
     __syncthreads();
+    SW_PHASE(pc, 0);   // staging
 
     const uint32_t x = lane;
     const bool vx = x < w;
@@ -557,6 +593,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     else if (q16 && !q8) strip_rows(std::true_type{}, std::false_type{});
     else if (fast) strip_rows(std::false_type{}, std::true_type{});
     else strip_rows(std::false_type{}, std::false_type{});
+    SW_PHASE(pc, 1);   // rows: draws, ballots, row labels, queue drains, counting
     seam[wave][lane] = lp;
     if (meas_prev) {
         // every site of the strip owns two bonds
@@ -568,7 +605,9 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         }
         if (q16 || fast) flush_state_bytes(packed, hist, d.q, lane);   // (fast: q <= 8, one word)
     }
+    SW_PHASE(pc, 2);   // measurement sums of the strip
     __syncthreads();
+    SW_PHASE(pc, 3);   // barrier
 
     // Seams: +y bonds from the last row of the strip above into this strip.
     if (wave > 0 && r0 < h) {
@@ -583,6 +622,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         enqueue(uq, V & ~R, up, first_prov);
     }
     drain(uq, P, lane, bad);
+    SW_PHASE(pc, 4);   // seams and the last drain
 
     // Tile record: bond words (tile-major), crossing-bond masks.
     gptr<uint32_t> rec = glb(d.edges) + (size_t)tile * edge_words(TY);
@@ -617,6 +657,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         }
     }
     __syncthreads();
+    SW_PHASE(pc, 5);   // bond words out, edge record, barrier
 
     // Edge sites find their tile-local roots (lane i takes the left and right
     // sites of strip row i; the first and last strips the top and bottom rows).
@@ -665,6 +706,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     claim(top, rootT);
     claim(bottom, rootB);
     __syncthreads();
+    SW_PHASE(pc, 6);   // edge roots, node claims, barrier
     if (tid == 0) rec[6] = tot[2];   // nodes of the tile
 
     // Tile labels out (16 bits), per site: the tile-local index of its
@@ -706,6 +748,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     } else {
         labels_out(std::false_type{});
     }
+    SW_PHASE(pc, 7);   // tile labels out
     // The edge record's slots, for the merge.
     const gptr<uint16_t> slots = (gptr<uint16_t>)(rec + 8);
     if (side) {
@@ -725,6 +768,8 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
             if (tid >= 1 && tid < d.q && hist[tid]) atomic_add_i64(&rp[1 + tid], hist[tid]);
         }
     }
+    SW_PHASE(pc, 8);   // slots, ring sums
+    SW_PHASE_FLUSH(pc, phase_table(PRESET ? 3u : 0u));
 }
 
 // ---------------------------------------------------------------------------
@@ -740,6 +785,7 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
     LatDesc d;
     uint32_t tile, lat;
     if (!pick(descs, map, idx, false, d, tile, lat)) return;
+    SW_PHASE_START(pc);
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t EW = edge_words(TY), NS = nslot(TY);
     const uint32_t n = d.ntiles * NS;
@@ -768,6 +814,7 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
         const uint32_t sa2 = sl[2 * TY + x], sb2 = slB[2 * TY + TX + x];
         const bool right = r < g.h && ((wr >> (r & 31u)) & 1u);
         const bool below = j == 0 && x < g.w && ((wb >> (x & 31u)) & 1u);
+        SW_PHASE(pc, 0);   // edge record and slots
         uint32_t a1 = INVALID, b1 = INVALID, a2 = INVALID, b2 = INVALID;
         if (right) {
             a1 = tile * NS + sa1;
@@ -794,11 +841,14 @@ __global__ __launch_bounds__(256) void k_merge(const LatDesc* descs, const WorkI
         uint32_t xs[4] = {a1, b1, a2, b2};
         uint64_t ws[4] = {u1 ? nodes[a1] : 0ull, u1 ? nodes[b1] : 0ull, u2 ? nodes[a2] : 0ull, u2 ? nodes[b2] : 0ull};
         n_find_m<4>(nodes, n, xs, ws, (u1 ? 3u : 0u) | (u2 ? 12u : 0u), bad);
+        SW_PHASE(pc, 1);   // node words, walks to the roots
         if (bad) break;
         uint64_t ha[2] = {ws[0], ws[2]}, hb[2] = {ws[1], ws[3]};
         n_hook2(nodes, n, ha, hb, bad);
+        SW_PHASE(pc, 2);   // hooks
     }
     if (bad) flag_error(d.err);
+    SW_PHASE_FLUSH(pc, phase_table(1u));
 }
 
 // ---------------------------------------------------------------------------
@@ -833,6 +883,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     LatDesc d;
     uint32_t tile, lat;
     if (!pick(descs, map, blockIdx.x, true, d, tile, lat)) return;
+    SW_PHASE_START(pc);
     const TileGeom g = tile_geom(d, tile, TY);
     const uint32_t t = *glb(d.counter) + k;
     const uint32_t tid = threadIdx.x, wave = wave_id(), lane = tid & 63u;
@@ -883,6 +934,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
             if (vcol) E[li0 + j * NW * TX] = (uint16_t)v[j];
             roots |= (v[j] >> 15) << j;   // 0 outside the tile
         }
+        SW_PHASE(pc, 0);   // labels in
         // The roots, one per lane and step (steps while any lane has one left):
         // a cluster inside the tile joins this wave's list, a node's slot must
         // name a node of the tile.
@@ -899,6 +951,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
             if (has && inside) my_list[nterm + lanes_below(m)] = (uint16_t)li;
             nterm += popc64(m);
         }
+        SW_PHASE(pc, 1);   // roots inside the tile listed
         // this wave's nodes find their roots' keys and join the list
         if (is_node) NK[nj] = key_of(n_find_from(nodes, n_nodes, node0 + nj, nw, bad));
         {
@@ -906,6 +959,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
             if (is_node) my_list[nterm + lanes_below(m)] = (uint16_t)(NODE_ENTRY | nj);
             nterm += popc64(m);
         }
+        SW_PHASE(pc, 2);   // node roots found
 
         // the states, 64 list entries at a time; lanes past the end work on a
         // copy they do not store
@@ -920,7 +974,9 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
             if (act && node) NK[idx & (NKN - 1u)] = st;
             if (act && !node) E[idx & (TY * TX - 1u)] = ROOT16 | RES16 | st;
         }
+        SW_PHASE(pc, 3);   // states drawn
         __syncthreads();
+        SW_PHASE(pc, 4);   // barrier
 
         // Every site follows in-tile pointers (each to a smaller tile index, so
         // the walk ends) to a root: resolved inside the tile, or a node whose
@@ -944,6 +1000,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
                 const uint32_t r = wave + NW * j;
                 if (vcol && (FULL || r < h)) bits |= (walk(j) & 1u) << j;
             }
+            SW_PHASE(pc, 5);   // walks
             // the reflected sites' angles in batches of eight: all loads of a
             // batch in flight together, then its stores
             const gptr<char> a_tile = (gptr<char>)(glb(d.ang) + (size_t)y0 * L + x0);
@@ -966,6 +1023,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
                 const uint32_t r = wave + NW * j;
                 e[j] = (vcol && (FULL || r < h)) ? walk(j) : 0u;
             }
+            SW_PHASE(pc, 5);   // walks
             gptr<uint8_t> s_p = (gptr<uint8_t>)s_tile + site0;
 #pragma unroll
             for (uint32_t j = 0; j < PER; ++j) {
@@ -977,7 +1035,9 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     };
     if (w == TX && h == TY) body(std::true_type{});
     else body(std::false_type{});
+    SW_PHASE(pc, 6);   // spins out (Potts) or reflections (XY)
     if (bad) flag_error(d.err);
+    SW_PHASE_FLUSH(pc, phase_table(XY ? 4u : 2u));
 
     // The ring record of the next sweep starts from zero.
     if (d.cap && tile == 0) {

@@ -69,6 +69,46 @@ __device__ __forceinline__ void atomic_add_i64(int64_t* p, uint64_t v)
                            __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// ------------------------------------------------------------ phase clocks
+// Profiling builds only (-DSW_PHASE_CLOCKS; the library is then built apart
+// from the product one): each wave sums the shader-clock ticks it spends
+// between consecutive marks, per phase, and its lane 0 adds the sums and a
+// wave count to a per-kernel table of NCOPY rows of PHASES + 1 counters (rows
+// picked by workgroup, to spread the atomics).  In every other build the marks
+// compile to nothing.
+constexpr uint32_t PHASES = 10;
+#ifdef SW_PHASE_CLOCKS
+struct PhaseClock {
+    uint64_t last;
+    uint32_t acc[PHASES];
+    __device__ PhaseClock() : last(__builtin_amdgcn_s_memtime())
+    {
+        for (uint32_t i = 0; i < PHASES; ++i) acc[i] = 0;
+    }
+    __device__ void mark(uint32_t i)
+    {
+        const uint64_t now = __builtin_amdgcn_s_memtime();
+        acc[i] += (uint32_t)(now - last);
+        last = now;
+    }
+    __device__ void flush(unsigned long long* table)
+    {
+        if ((threadIdx.x & 63u) != 0) return;
+        unsigned long long* row = table + (blockIdx.x % NCOPY) * (PHASES + 1);
+        for (uint32_t i = 0; i < PHASES; ++i)
+            if (acc[i]) atomicAdd(&row[i], (unsigned long long)acc[i]);
+        atomicAdd(&row[PHASES], 1ull);
+    }
+};
+#define SW_PHASE_START(pc) PhaseClock pc
+#define SW_PHASE(pc, i) pc.mark(i)
+#define SW_PHASE_FLUSH(pc, table) pc.flush(table)
+#else
+#define SW_PHASE_START(pc)
+#define SW_PHASE(pc, i) ((void)0)
+#define SW_PHASE_FLUSH(pc, table) ((void)0)
+#endif
+
 constexpr uint32_t LDS_CAP = 1u << 15;     // cap of union retries in LDS (> sites of a tile)
 
 // ------------------------------------------------------- LDS union-find
