@@ -665,7 +665,8 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     // forest: it takes the next slot (in no particular order: a node's word
     // carries its key), writes the node's word (a root of its own, keyed by its
     // site index) and tags the root's LDS entry ROOT16 | slot, which the labels
-    // and the edge record copy.  Walks stop at tagged entries.
+    // and the edge record copy.  Walks stop at tagged entries (all walks end
+    // before the first claim).
     // a site index fits 32 bits (N <= 2^32) and y, L fit 24 bits
     auto global_index = [&](uint32_t la) { return __umul24(y0 + la / TX, L) + x0 + la % TX; };
     const uint32_t node0 = tile * nslot(TY);
@@ -678,20 +679,17 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         bad |= !(p & ROOT16) && p != li;
         return li;
     };
-    // claim root r if it is still untagged: one swap per lane, then the wave's
-    // winners take consecutive slots with one LDS atomic
+    // A claim of root r sets the ROOT16 bit of its entry with one LDS atomic
+    // OR on the entry's 32-bit word: the lane that finds the bit clear is the
+    // first and wins; an entry tagged already keeps its value (a slot stored
+    // by another winner is never overwritten).  The four claims of a lane go
+    // out together, then the wave's winners take consecutive slots with one
+    // LDS atomic and tag their roots ROOT16 | slot.
     auto claim = [&](bool want, uint32_t r) {
-        const bool won = want && lds_cas16(P, r, r, ROOT16 | NOSLOT, bad) == r;
-        const uint64_t m = ballot(won);
-        if (!m) return;
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&tot[2], popc64(m));
-        base = __builtin_amdgcn_readfirstlane(base);
-        if (won) {
-            const uint32_t slot = base + lanes_below(m);
-            glb(d.nodes)[node0 + slot] = ((uint64_t)global_index(r) << 32) | (node0 + slot);
-            lds_st(&P[r], ROOT16 | slot);
-        }
+        if (!want) return false;
+        const uint32_t sh = (r & 1u) * 16u;
+        const uint32_t old = atomicOr(reinterpret_cast<uint32_t*>(P) + (r >> 1), ROOT16 << sh);
+        return ((old >> sh) & 0xFFFFu) == r;
     };
     const bool side = r0 < r1 && lane < r1 - r0;
     const bool top = r0 == 0 && r0 < r1 && vx;
@@ -701,10 +699,23 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     const uint32_t rootL = side ? edge_root(rs * TX) : 0u;
     const uint32_t rootT = top ? edge_root(x) : 0u;
     const uint32_t rootB = bottom ? edge_root((h - 1) * TX + x) : 0u;
-    claim(side, rootR);
-    claim(side, rootL);
-    claim(top, rootT);
-    claim(bottom, rootB);
+    const bool wR = claim(side, rootR), wL = claim(side, rootL), wT = claim(top, rootT), wB = claim(bottom, rootB);
+    {
+        const uint64_t mR = ballot(wR), mL = ballot(wL), mT = ballot(wT), mB = ballot(wB);
+        const uint32_t nR = popc64(mR), nL = popc64(mL), nT = popc64(mT), n_won = nR + nL + nT + popc64(mB);
+        uint32_t base = 0;
+        if (lane == 0 && n_won) base = atomicAdd(&tot[2], n_won);
+        base = __builtin_amdgcn_readfirstlane(base);
+        auto assign = [&](bool won, uint32_t r, uint32_t slot) {
+            if (!won) return;
+            glb(d.nodes)[node0 + slot] = ((uint64_t)global_index(r) << 32) | (node0 + slot);
+            lds_st(&P[r], ROOT16 | slot);
+        };
+        assign(wR, rootR, base + lanes_below(mR));
+        assign(wL, rootL, base + nR + lanes_below(mL));
+        assign(wT, rootT, base + nR + nL + lanes_below(mT));
+        assign(wB, rootB, base + nR + nL + nT + lanes_below(mB));
+    }
     __syncthreads();
     SW_PHASE(pc, 6);   // edge roots, node claims, barrier
     if (tid == 0) rec[6] = tot[2];   // nodes of the tile

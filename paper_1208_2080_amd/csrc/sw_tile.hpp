@@ -139,25 +139,6 @@ __device__ __forceinline__ void lds_st(uint16_t* p, uint32_t v)
     __hip_atomic_store(p, (uint16_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Entry i of P set to `desired` if it holds `expect` (as a compare-and-swap
-// would); returns the entry's value before.  A failed 32-bit swap means the
-// word changed, so some lane made progress.
-__device__ __forceinline__ uint32_t lds_cas16(uint16_t* P, uint32_t i, uint32_t expect, uint32_t desired, bool& bad)
-{
-    uint32_t* const w = reinterpret_cast<uint32_t*>(P) + (i >> 1);
-    const uint32_t sh = (i & 1u) * 16u;
-    uint32_t cur = lds_ld(w);
-    for (uint32_t it = 0; it < LDS_CAP; ++it) {
-        const uint32_t old = (cur >> sh) & 0xFFFFu;
-        if (old != expect) return old;
-        const uint32_t seen = atomicCAS(w, cur, (cur & ~(0xFFFFu << sh)) | (desired << sh));
-        if (seen == cur) return old;
-        cur = seen;
-    }
-    bad = true;
-    return expect;
-}
-
 // min(P[i], v) into entry i; returns the entry's value before.
 __device__ __forceinline__ uint32_t lds_min16(uint16_t* P, uint32_t i, uint32_t v, bool& bad)
 {
@@ -175,27 +156,35 @@ __device__ __forceinline__ uint32_t lds_min16(uint16_t* P, uint32_t i, uint32_t 
     return v;
 }
 
-// Root of x while unions may still run, with path splitting: every visited
+// Roots of a and b while unions may still run, both walked in the same loop
+// so that their LDS round trips overlap, with path splitting: every visited
 // node is pointed at its grandparent (a stored value is always an ancestor,
 // so races with other finds and hooks are benign).
-__device__ __forceinline__ uint32_t lds_find(uint16_t* P, uint32_t x, bool& bad)
+__device__ __forceinline__ void lds_find2(uint16_t* P, uint32_t& a, uint32_t& b, bool& bad)
 {
-    uint32_t p = lds_ld(&P[x]);
-    while (p < x) {
-        const uint32_t gp = lds_ld(&P[p]);
-        lds_st(&P[x], gp);
-        x = p;
-        p = gp;
+    uint32_t pa = lds_ld(&P[a]), pb = lds_ld(&P[b]);
+    while (pa < a || pb < b) {
+        const bool sa = pa < a, sb = pb < b;
+        const uint32_t ga = sa ? lds_ld(&P[pa]) : pa;
+        const uint32_t gb = sb ? lds_ld(&P[pb]) : pb;
+        if (sa) {
+            lds_st(&P[a], ga);
+            a = pa;
+            pa = ga;
+        }
+        if (sb) {
+            lds_st(&P[b], gb);
+            b = pb;
+            pb = gb;
+        }
     }
-    bad |= p != x;
-    return x;
+    bad |= pa != a || pb != b;
 }
 
 __device__ void lds_union(uint16_t* P, uint32_t a, uint32_t b, bool& bad)
 {
     for (uint32_t it = 0; it < LDS_CAP; ++it) {
-        a = lds_find(P, a, bad);
-        b = lds_find(P, b, bad);
+        lds_find2(P, a, b, bad);
         if (a == b) return;
         const uint32_t hi = max(a, b), lo = min(a, b);
         const uint32_t old = lds_min16(P, hi, lo, bad);
