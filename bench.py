@@ -28,12 +28,16 @@ FP64_PEAK_TFLOPS = 78.6          # MI355X dense FP64 vector, vendor figure
 # once: sin and cos of the angle (37), the projection (3), the two bond tests
 # (7: the FP32 estimates not counted), the measurement terms (30)
 XY_BOND_FLOPS_PER_SITE = 77
-# algorithmic bytes per site of one launch (uint8 spins, uint16 tile labels, 2-bit bonds)
+# Algorithmic bytes per site of one launch: the byte model of the method's
+# stated layout (uint8 spins, uint32 labels, 2-bit bond masks).  The kernels
+# store 16-bit tile labels, so they move 2 B/site less each than this model
+# counts (3.25 and 3.0 B/site); the measured bytes are the roofline's
+# `traffic`.
 KERNEL_BYTES_PER_SITE = {
-    "k_bond_label": 1.0 + 0.25 + 2.0,   # read spins, write bond planes, write tile labels
-    "k_flip": 2.0 + 1.0,                # read tile labels, write spins
+    "k_bond_label": 1.0 + 0.25 + 4.0,   # read spins, write bond planes, write labels
+    "k_flip": 4.0 + 1.0,                # read labels, write spins
 }
-SWEEP_BYTES_PER_SITE = 6.25
+SWEEP_BYTES_PER_SITE = 10.25
 PHASE_KERNELS = ["k_bond_label", "k_merge", "k_flip", "k_measure+k_bump"]
 
 
