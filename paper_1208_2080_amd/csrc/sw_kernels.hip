@@ -34,15 +34,20 @@ constexpr uint32_t SPW = TX + 4;           // LDS row stride of staged spins (by
 // Lane l's bit of a wave-uniform mask, as a lane predicate.
 __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
-// Sum over the wave of a per-lane value below 2^BITS, bit plane by bit plane
-// (one ballot per plane: cheaper than 64 atomics on one LDS word).
-template <int BITS>
-__device__ __forceinline__ uint32_t wave_sum_small(uint32_t v)
+// Sum over the wave of a per-lane value (all 64 lanes active), in vector
+// instructions only: pairs and quads by quad permutes, rows of 16 by half-row
+// and row mirrors, then the rows' sums broadcast into row 3 (row_bcast:15 into
+// rows 1 and 3, row_bcast:31 into rows 2 and 3), so lane 63 holds the total.
+// Where the scalar unit is the busier one this beats a ballot per bit plane.
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v)
 {
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < BITS; ++k) s += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64((v >> k) & 1u)) << k;
-    return s;
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);            // quad_perm [1,0,3,2]
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);            // quad_perm [2,3,0,1]
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x141, 0xF, 0xF, false);           // row_half_mirror
+    v += (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x140, 0xF, 0xF, false);           // row_mirror
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);     // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);     // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // Number of set bits of a wave-uniform mask below this lane.
@@ -261,7 +266,7 @@ __device__ __forceinline__ void count_state_bytes(uint64_t (&w)[2], bool valid, 
 __device__ __forceinline__ void flush_state_bytes(const uint64_t (&w)[2], uint32_t* hist, uint32_t q, uint32_t lane)
 {
     for (uint32_t c = 1; c < q; ++c) {
-        const uint32_t n = wave_sum_small<5>((uint32_t)(w[c >> 3] >> (8u * (c & 7u))) & 0xFFu);
+        const uint32_t n = wave_sum((uint32_t)(w[c >> 3] >> (8u * (c & 7u))) & 0xFFu);
         if (lane == 0 && n) atomicAdd(&hist[c], n);
     }
 }
@@ -597,10 +602,10 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     seam[wave][lane] = lp;
     if (meas_prev) {
         // every site of the strip owns two bonds
-        const uint32_t eq = wave_sum_small<6>(n_eq);   // a lane counts at most 2 RPW <= 32 pairs
+        const uint32_t eq = wave_sum(n_eq);
         if (lane == 0 && r0 < r1) atomicAdd(&tot[0], 2u * w * (r1 - r0) - eq);
         if (q2 && !fast) {
-            const uint32_t n1 = wave_sum_small<6>(ones);   // a lane counts at most TY / 4 <= 32 rows
+            const uint32_t n1 = wave_sum(ones);
             if (lane == 0 && n1) atomicAdd(&hist[1], n1);
         }
         if (q16 || fast) flush_state_bytes(packed, hist, d.q, lane);   // (fast: q <= 8, one word)
@@ -632,7 +637,7 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         const uint64_t word = (j < 2 * TY && r < h) ? rb[r][j / TY] : 0ull;
         if (!PRESET && j < 2 * TY && r < h) bw[j] = word;
         if (meas) {
-            const uint32_t n = wave_sum_small<7>(popc64(word));   // active bonds
+            const uint32_t n = wave_sum(popc64(word));   // active bonds
             if (lane == 0 && n) atomicAdd(&tot[1], n);
         }
     }
