@@ -775,13 +775,18 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
     if (bottom) slots[2 * TY + x] = P[rootB] & ~ROOT16;
     if (bad) flag_error(d.err);
 
-    if (meas) {
+    // the workgroup's sums into the ring, by wave 0 alone (the slot's modulo is
+    // scalar work the other waves need not repeat)
+    if (meas && wave == 0) {
         const uint32_t copy = blockIdx.x % NCOPY;
-        if (tid == 0) atomic_add_i64(&ring_record(d, t, copy)[1], tot[1]);
+        const uint32_t slot = t % d.cap, prev = slot ? slot - 1u : d.cap - 1u;
+        int64_t* const rc = d.ring + ((size_t)slot * NCOPY + copy) * ring_stride(d.q);
+        if (lane == 0) atomic_add_i64(&rc[1], tot[1]);
         if (meas_prev) {
-            int64_t* rp = ring_record(d, t - 1, copy);
-            if (tid == 0) atomic_add_i64(&rp[0], tot[0]);
-            if (tid >= 1 && tid < d.q && hist[tid]) atomic_add_i64(&rp[1 + tid], hist[tid]);
+            int64_t* const rp = d.ring + ((size_t)prev * NCOPY + copy) * ring_stride(d.q);
+            if (lane == 0) atomic_add_i64(&rp[0], tot[0]);
+            for (uint32_t c = lane; c < d.q; c += 64)
+                if (c >= 1 && hist[c]) atomic_add_i64(&rp[1 + c], hist[c]);
         }
     }
     SW_PHASE(pc, 8);   // slots, ring sums

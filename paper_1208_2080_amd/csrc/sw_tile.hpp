@@ -22,7 +22,8 @@ struct TileGeom {
 __device__ __forceinline__ TileGeom tile_geom(const LatDesc& d, uint32_t tile, uint32_t ty_rows)
 {
     TileGeom g;
-    g.ty = tile / d.ntx;
+    // tiles per row: L / 64 for a power-of-two L >= 64 (a shift), else a division
+    g.ty = d.log2L >= 6 ? tile >> (d.log2L - 6u) : tile / d.ntx;
     g.tx = tile - g.ty * d.ntx;
     g.x0 = g.tx * TX;
     g.y0 = g.ty * ty_rows;
