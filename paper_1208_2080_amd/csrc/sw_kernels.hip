@@ -330,8 +330,11 @@ __device__ __forceinline__ uint32_t row_labels(uint16_t* P, uint32_t* rl, UnionQ
                                                uint64_t validm, uint64_t hx, uint64_t V, uint64_t hprev, uint32_t lp)
 {
     const uint64_t C = hx << 1;                 // bit x: bond (x-1) -> x
-    const uint64_t S = ~C & validm;             // first sites of runs
-    const uint32_t ri = lanes_below(S >> 1);    // number of run starts in 1..x = run index of x
+    const uint64_t S = ~C & validm;             // first sites of runs (site 0 always is one)
+    // run index of x = run starts in 0..x, less one: counted from an initial
+    // value of (x starts a run) - 1, with no scalar shift of S
+    const uint32_t ri = __builtin_amdgcn_mbcnt_hi((uint32_t)(S >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)S, (uint32_t)lane_in(S) - 1u));
     const uint32_t fresh = r * TX + x;
     // lanes talk through the slots, so these accesses must not be folded away;
     // a run's first site offers itself and every +y bond offers the label
