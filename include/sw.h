@@ -161,8 +161,10 @@ int sw_read_spins(sw_lattice* h, uint8_t* host_out);
  * `sweep` are dropped.  Synchronises the stream. */
 int sw_load_spins(sw_lattice* h, const uint8_t* host_in, uint32_t sweep);
 
-/* Cluster labels of the last sweep: N uint32, label[i] = smallest site index
- * of i's cluster.  Needs at least one sweep since init / load.  Synchronises. */
+/* Cluster labels of the last sweep (the labelling of Sec. 2 step (2), each
+ * cluster labelled by its smallest site index as in the Hoshen-Kopelman
+ * paragraph): N uint32, label[i] = smallest site index of i's cluster.  Needs
+ * at least one sweep since init / load.  Synchronises. */
 int sw_read_labels(sw_lattice* h, uint32_t* host_out);
 
 /* The bonds activated in step (1) of the last sweep (Sec. 2) as two bit planes
