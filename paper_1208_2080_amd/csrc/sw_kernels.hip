@@ -56,12 +56,6 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t m)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Value of the neighbouring lane of the pair (lane ^ 1).
-__device__ __forceinline__ uint32_t swap_pair(uint32_t v)
-{
-    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-}
-
 // ------------------------------------------------------ edge forest (global)
 // One node per tile-local cluster that touches a tile edge.  A node's word is
 // (key << 32) | parent: parent is a node id, key the smallest site index of the

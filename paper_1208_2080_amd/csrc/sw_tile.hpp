@@ -15,6 +15,12 @@ constexpr uint32_t waves_of() { return TY == 128 ? 8u : 4u; }
 template <int TY>
 constexpr uint32_t threads_of() { return 64u * waves_of<TY>(); }
 
+// Value of the neighbouring lane of the pair (lane ^ 1).
+__device__ __forceinline__ uint32_t swap_pair(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+}
+
 struct TileGeom {
     uint32_t tx, ty, x0, y0, w, h;
 };

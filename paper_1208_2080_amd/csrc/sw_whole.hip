@@ -8,14 +8,18 @@
 // kernels, so results are bit-identical to them (and to the oracle):
 //   (1) bonds: one Philox call per site pair (counter (i >> 1, 0, t, 0), the
 //       pair's words 2b, 2b + 1 for site parity b) against the threshold;
+//       with L even a lane pair draws for two rows at once (lane 2m the pair
+//       of row y, lane 2m + 1 that of row y + 1, halves swapped), as in the
+//       tile kernels, so each call is made once;
 //   (2) labels: every wave takes whole rows; within a row (64 columns at a
 //       time) a site points at the first site of its run of +x bonds (a
 //       ballot, no atomics), then union-find joins the runs along the +y
 //       bonds (one bond per pair of runs), across 64-column chunks and across
 //       the periodic edges, the larger root hooked under the smaller, so each
 //       cluster's root is its smallest site;
-//   (3) every root draws its cluster's state (counter (root, 0, t, 1)) and
-//       every site copies its root's;
+//   (3) every root draws its cluster's state (counter (root, 0, t, 1)), the
+//       roots gathered into a per-wave list and drawn 64 at a time, and every
+//       site copies its root's;
 // then the measurement of the new configuration into the ring record of the
 // sweep (written whole into copy 0, with the whole-record flag).  After the
 // last sweep: the spins go back to global memory, and on request the labels
@@ -98,30 +102,52 @@ __global__ __launch_bounds__(whole_threads<LMAX>()) void k_whole(const LatDesc* 
         const uint32_t t = t0 + k;
         if (tid < 256) hist[tid] = 0;
         if (tid < 2) tot[tid] = 0;
-        // (1) bonds, row by row (wave w takes rows w, w + NW, ...; 64 columns
-        // per pass, one column per lane); each site's draws come from its
-        // pair's Philox call, and it points at the first site of its run
+        // (1) bonds, row by row (64 columns per pass, one column per lane), each
+        // site's two draws from its pair's Philox call; each site points at the
+        // first site of its run
         uint32_t active = 0;
-        for (uint32_t y = wave; y < L; y += NW) {
-            for (uint32_t x0 = 0; x0 < L; x0 += TX) {
-                const uint32_t x = x0 + lane, i = y * L + x;
-                const bool v = x < L;
-                bool bx = false, by = false;
-                if (v) {
-                    const u32x4 w = philox4x32_10(i >> 1, 0u, t, 0u, d.key0, d.key1);
-                    const uint32_t wx = (i & 1u) ? w.z : w.x, wy = (i & 1u) ? w.w : w.y;
-                    const uint32_t si = s[i];
-                    bx = d.thr_nz && si == s[right(i, x)] && wx <= d.thr_m1;
-                    by = d.thr_nz && si == s[down(i, x, y)] && wy <= d.thr_m1;
-                    bnd[i] = (uint8_t)((bx ? 1u : 0u) | (by ? 2u : 0u));
-                }
-                active += (uint32_t)bx + (uint32_t)by;
-                const uint64_t validm = ballot(v);
-                const uint64_t C = (ballot(bx) << 1) & validm;   // bit x: bond (x-1) -> x inside the pass
-                const uint64_t S = ~C & validm;                  // first sites of runs
-                const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-                if (v) P[i] = (uint16_t)(y * L + x0 + 63u - (uint32_t)__builtin_clzll(S & upto));
+        {
+        auto bond_row = [&](uint32_t y, uint32_t x0, uint32_t wx, uint32_t wy) {
+            const uint32_t x = x0 + lane, i = y * L + x;
+            const bool v = x < L;
+            bool bx = false, by = false;
+            if (v) {
+                const uint32_t si = s[i];
+                bx = d.thr_nz && si == s[right(i, x)] && wx <= d.thr_m1;
+                by = d.thr_nz && si == s[down(i, x, y)] && wy <= d.thr_m1;
+                bnd[i] = (uint8_t)((bx ? 1u : 0u) | (by ? 2u : 0u));
             }
+            active += (uint32_t)bx + (uint32_t)by;
+            const uint64_t validm = ballot(v);
+            const uint64_t C = (ballot(bx) << 1) & validm;   // bit x: bond (x-1) -> x inside the pass
+            const uint64_t S = ~C & validm;                  // first sites of runs
+            const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+            if (v) P[i] = (uint16_t)(y * L + x0 + 63u - (uint32_t)__builtin_clzll(S & upto));
+        };
+        if ((L & 1u) == 0) {
+            // wave w takes the row pairs (2w, 2w + 1), (2w + 2 NW, ...), ...; a
+            // pass's valid lanes come in whole pairs (L and 64 are even)
+            const bool odd = lane & 1u;
+            for (uint32_t y = 2 * wave; y < L; y += 2 * NW) {
+                for (uint32_t x0 = 0; x0 < L; x0 += TX) {
+                    const uint32_t pair = ((odd ? (y + 1) * L : y * L) + x0 + (lane & ~1u)) >> 1;
+                    const u32x4 q4 = philox4x32_10(pair, 0u, t, 0u, d.key0, d.key1);
+                    const uint32_t recv0 = swap_pair(odd ? q4.x : q4.z);
+                    const uint32_t recv1 = swap_pair(odd ? q4.y : q4.w);
+                    bond_row(y, x0, odd ? recv0 : q4.x, odd ? recv1 : q4.y);
+                    bond_row(y + 1, x0, odd ? q4.z : recv0, odd ? q4.w : recv1);
+                }
+            }
+        } else {
+            // wave w takes rows w, w + NW, ...; each lane its own site's call
+            for (uint32_t y = wave; y < L; y += NW) {
+                for (uint32_t x0 = 0; x0 < L; x0 += TX) {
+                    const uint32_t i = y * L + x0 + lane;
+                    const u32x4 w = philox4x32_10(i >> 1, 0u, t, 0u, d.key0, d.key1);
+                    bond_row(y, x0, (i & 1u) ? w.z : w.x, (i & 1u) ? w.w : w.y);
+                }
+            }
+        }
         }
         __syncthreads();
         // (2) unions, queued per wave and run 64 at a time with every lane busy
@@ -189,9 +215,31 @@ __global__ __launch_bounds__(whole_threads<LMAX>()) void k_whole(const LatDesc* 
             lds_st(&P[i], r);
         }
         __syncthreads();
-        // (3) roots draw their clusters' states, then every site takes its root's
-        for (uint32_t i = tid; i < N; i += NT)
-            if (P[i] == i) s[i] = (uint8_t)cluster_state(d, i, t);
+        // (3) roots draw their clusters' states, gathered into the wave's queue
+        // (free after the unions) and drawn 64 at a time, then every site takes
+        // its root's
+        {
+            uint32_t nr = 0;   // wave-uniform
+            auto draw = [&]() {
+                for (uint32_t j0 = 0; j0 < nr; j0 += 64) {
+                    const uint32_t j = j0 + lane;
+                    if (j < nr) {
+                        const uint32_t r = UQ[wave][j];
+                        s[r] = (uint8_t)state_of_draw(philox4x32_10(r, 0u, t, 1u, d.key0, d.key1).x, q);
+                    }
+                }
+                nr = 0;
+            };
+            for (uint32_t i0 = 0; i0 < N; i0 += NT) {
+                const uint32_t i = i0 + tid;
+                const bool root = i < N && P[i] == i;
+                const uint64_t m = ballot(root);
+                if (root) UQ[wave][nr + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = i;
+                nr += (uint32_t)__popcll(m);
+                if (nr > QCAP - 64) draw();
+            }
+            draw();
+        }
         __syncthreads();
         for (uint32_t i = tid; i < N; i += NT) {
             const uint32_t r = P[i];
