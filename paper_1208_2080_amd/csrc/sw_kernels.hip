@@ -940,35 +940,32 @@ __global__ __launch_bounds__(threads_of<TY>()) __attribute__((amdgpu_waves_per_e
         const bool is_node = nj < n_used;
         const uint64_t nw = is_node ? nodes[node0 + nj] : 0ull;
 
-        // row j of this wave: tile index li0 + j NW TX.  The labels go to E; bit
-        // j of `roots` marks a root (tagged ROOT16: a node, or a cluster inside
-        // the tile).  A pointer to a larger site is found by the walk below.
+        // row j of this wave: tile index li0 + j NW TX.  The labels go to E.  A
+        // pointer to a larger site is found by the walk below.
         const uint32_t li0 = wave * TX + col;
-        uint32_t roots = 0;
 #pragma unroll
         for (uint32_t j = 0; j < PER; ++j) {
             const uint32_t r = wave + NW * j;
             if (!FULL && r >= h) continue;
             if (vcol) E[li0 + j * NW * TX] = (uint16_t)v[j];
-            roots |= (v[j] >> 15) << j;   // 0 outside the tile
         }
         SW_PHASE(pc, 0);   // labels in
-        // The roots, one per lane and step (steps while any lane has one left):
-        // a cluster inside the tile joins this wave's list, a node's slot must
-        // name a node of the tile.
+        // The roots (tagged ROOT16), one ballot per row: a cluster inside the
+        // tile joins this wave's list, a node's slot must name a node of the
+        // tile (labels outside the tile are 0).  Lanes with nothing to list store
+        // to their scratch slot instead of branching around the store.
         uint32_t nterm = 0;   // wave-uniform
-        while (ballot(roots != 0)) {
-            const bool has = roots != 0;
-            const uint32_t j = __builtin_ctz(roots | (1u << PER));
-            roots &= roots - 1u;
-            const uint32_t li = li0 + j * NW * TX;
-            const uint32_t vv = has ? (uint32_t)E[li & (TY * TX - 1u)] : 0u;
-            const bool inside = vv == (ROOT16 | NOSLOT);
-            bad |= has && !inside && (vv & ~ROOT16) >= n_used;
-            const uint64_t m = ballot(has && inside);
-            if (has && inside) my_list[nterm + lanes_below(m)] = (uint16_t)li;
+        uint32_t badv = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < PER; ++j) {
+            const uint32_t r = wave + NW * j;
+            if (!FULL && r >= h) continue;
+            const uint64_t m = ballot(v[j] == (ROOT16 | NOSLOT));
+            badv |= (v[j] - (ROOT16 + n_used)) < (NOSLOT - n_used) ? 1u : 0u;
+            my_list[lane_in(m) ? nterm + lanes_below(m) : PER * TX + 64 + lane] = (uint16_t)(li0 + j * NW * TX);
             nterm += popc64(m);
         }
+        bad |= badv != 0;
         SW_PHASE(pc, 1);   // roots inside the tile listed
         // this wave's nodes find their roots' keys and join the list
         if (is_node) NK[nj] = key_of(n_find_from(nodes, n_nodes, node0 + nj, nw, bad));
