@@ -48,9 +48,14 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        if _stale():
-            build(force=True)
-        L = ctypes.CDLL(_LIB)
+        # SW_ORACLE_LIB: another build of these sources to load instead (the
+        # test that plants mistakes in a copy of the oracle runs the pins on it)
+        path = os.environ.get("SW_ORACLE_LIB")
+        if not path:
+            if _stale():
+                build(force=True)
+            path = _LIB
+        L = ctypes.CDLL(path)
         u8p = ctypes.POINTER(ctypes.c_uint8)
         u32p = ctypes.POINTER(ctypes.c_uint32)
         i64p = ctypes.POINTER(ctypes.c_int64)
