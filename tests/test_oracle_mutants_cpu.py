@@ -89,8 +89,10 @@ def _build(tmp, name, src_file, old, new):
 def _pins(job):
     so, files = job
     env = dict(os.environ, SW_ORACLE_LIB=so)
+    # each run keeps its temporary files apart (concurrent sessions prune a shared one)
     r = subprocess.run([sys.executable, "-m", "pytest", *[os.path.join(ROOT, "tests", f) for f in files], "-q",
-                        "-p", "no:cacheprovider", "--timeout", "300"],
+                        "-p", "no:cacheprovider", "--timeout", "300",
+                        "--basetemp", os.path.join(os.path.dirname(so), "pytest-tmp")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     return r.returncode, r.stdout[-2000:]
 
