@@ -209,3 +209,23 @@ def test_whole_lattice_tile_rows():
     assert _ws(64, ty=binding.SW_TILE_WHOLE) == _ws(64)          # the same workspace layout
     assert _ws(64, ty=5) == 0
     assert _xy_ws(64, ty=binding.SW_TILE_WHOLE) == 0
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built HIP library every entry point raises; nothing falls
+    back to another implementation (fresh interpreter, library path unbuilt)."""
+    import subprocess
+    import sys
+    code = (
+        "from paper_1208_2080_amd import binding\n"
+        f"binding.LIB_PATH = {str(tmp_path / 'libswmi.so')!r}\n"
+        "for call in (binding.lib, lambda: binding.threshold(1.0)):\n"
+        "    try:\n"
+        "        call()\n"
+        "    except RuntimeError as e:\n"
+        "        assert 'missing' in str(e), e\n"
+        "    else:\n"
+        "        raise SystemExit('no error without the library')\n"
+        "print('raised')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "raised" in r.stdout, r.stdout + r.stderr
